@@ -1,0 +1,187 @@
+/*
+ * fastlec_es.h - exact simulation (ES) of And-Inverter-Graph miters on AMD
+ * Instinct MI355X (gfx950).  C ABI; plain pointers and sizes only.
+ *
+ * What is computed.  A circuit is a latch-free AIG (paper, Section 2.1).  It
+ * is read as a miter: its miter value at an input assignment is the OR of all
+ * of its outputs, and the circuit is EQUIVALENT iff that value is 0 for every
+ * assignment (paper, Section 2.1: XOR paired outputs, OR the results,
+ * equivalent iff the miter output is identically zero).  Exact simulation
+ * enumerates every assignment of the n primary inputs and checks the miter
+ * output (paper, Section 2.2, "Exact Simulation"); the result is either
+ * EQUIVALENT or the counterexample with the lowest index.
+ *
+ * Patterns.  Pattern p in [0, 2^n) assigns bit i of p to primary input i (the
+ * i-th input of the AIGER file).  A "word" is 64 consecutive patterns:
+ * word w holds patterns 64w .. 64w+63.  The space has W = max(1, 2^(n-6))
+ * words; for n < 6 word 0 holds every pattern.  n must be at most 63.
+ *
+ * Errors.  Every int-returning function returns FASTLEC_OK (0) or a negative
+ * status.  No C++ exception crosses this boundary.  fastlec_es_last_error()
+ * returns a message for the last failing call on the calling thread.
+ *
+ * Threads and streams.  A circuit handle is immutable after loading; several
+ * threads may check the same handle at once, on the same or different streams.
+ * Calls block the calling host thread until their results are on the host.
+ */
+#ifndef FASTLEC_ES_H
+#define FASTLEC_ES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+enum {
+    FASTLEC_OK = 0,
+    FASTLEC_ERR_PARSE = -1,        /* malformed AIGER (bad header, literal, cycle, undefined variable) */
+    FASTLEC_ERR_UNSUPPORTED = -2,  /* latches or other sequential sections, or more than 63 inputs */
+    FASTLEC_ERR_NOMEM = -3,        /* host or device allocation failed */
+    FASTLEC_ERR_DEVICE = -4,       /* HIP runtime or hipRTC failure, or no usable gfx950 device */
+    FASTLEC_ERR_INVALID = -5,      /* bad argument (null pointer, empty range, unknown option value) */
+    FASTLEC_CANCELLED = -6,        /* the cancel flag was raised; result carries progress */
+    FASTLEC_TIMEOUT = -7,          /* the deadline passed; result carries progress */
+    FASTLEC_REJECTED = -8          /* server: the job can never fit the memory budget */
+};
+
+/* ---- verdicts ------------------------------------------------------------ */
+enum { FASTLEC_EQUIVALENT = 0, FASTLEC_NONEQUIVALENT = 1 };
+
+/* ---- kernels ------------------------------------------------------------- */
+enum {
+    FASTLEC_KERNEL_AUTO = 0,        /* specialized for large spaces, interpreter otherwise */
+    FASTLEC_KERNEL_INTERP = 1,      /* generic interpreter, node values in LDS */
+    FASTLEC_KERNEL_SPECIALIZED = 2, /* straight-line kernel compiled for this circuit, values in VGPRs */
+    FASTLEC_KERNEL_INTERP_HBM = 3   /* generic interpreter, node values in device memory */
+};
+
+typedef struct fastlec_es_circuit fastlec_es_circuit; /* opaque, immutable after load */
+
+typedef struct {
+    uint32_t num_pis;          /* n */
+    uint32_t num_ands;         /* AND gates in the file */
+    uint32_t num_ands_tfi;     /* AND gates in the fan-in cone of the outputs (N) */
+    uint32_t num_outputs;
+    uint32_t peak_live_slots;  /* S: node values alive at once under the planned order */
+    uint32_t num_instrs;       /* interpreter instructions (N plus output-only instructions) */
+    uint32_t levels;           /* logic depth of the cone */
+    uint32_t reserved;
+} fastlec_es_info;
+
+typedef struct {
+    int device;                /* HIP device ordinal */
+    void *hip_stream;          /* hipStream_t to run on; NULL = the library's stream for the device */
+    uint32_t words_per_thread; /* interpreter: 32-bit pattern words per lane per slot (1, 2, 4); 0 = tuned */
+    uint32_t tile_words;       /* 64-pattern words claimed per work unit; 0 = tuned */
+    uint32_t wg_size;          /* threads per workgroup (64..1024, multiple of 64); 0 = tuned */
+    int kernel;                /* FASTLEC_KERNEL_* */
+    uint64_t begin_word;       /* check words [begin_word, end_word); 0,0 = the whole space */
+    uint64_t end_word;
+    double deadline_s;         /* > 0: stop with FASTLEC_TIMEOUT after this many seconds */
+    volatile int *cancel_flag; /* host memory; nonzero = stop with FASTLEC_CANCELLED; may be NULL */
+    void *dev_scratch;         /* optional caller-owned device memory for control blocks (>= 4096 B) */
+    size_t dev_scratch_bytes;
+} fastlec_es_options;
+
+typedef struct {
+    int32_t verdict;             /* FASTLEC_EQUIVALENT / FASTLEC_NONEQUIVALENT, or a negative status in batch */
+    uint32_t reserved;
+    uint64_t cex;                /* lowest failing pattern in the range; valid iff NONEQUIVALENT */
+    uint64_t patterns_evaluated; /* patterns whose miter value the answer establishes: the whole range when
+                                    EQUIVALENT (2^n for a full check), range start .. cex when not */
+    uint64_t next_word;          /* resume point: first word not known to be clean */
+    double plan_ms;              /* host planning time (at load) */
+    double compile_ms;           /* specialized-kernel compile time paid by this call (0 if cached) */
+    double kernel_ms;            /* device time of the simulation kernel */
+} fastlec_es_result;
+
+/* Fill *opts with defaults: device 0, library stream, tuned schedule, whole space. */
+void fastlec_es_options_init(fastlec_es_options *opts);
+
+/* Load an AIGER file from memory (ASCII "aag" or binary "aig", detected from the header),
+ * validate it (no latches, n <= 63, topologically orderable), extract the output cone and
+ * plan it (evaluation order, reference-count slot map, instruction stream; paper,
+ * Section 3.3 "Instructionalized ES").  bytes: host memory, len bytes, caller-owned, not
+ * retained.  *out receives a handle owned by the caller until fastlec_es_free. */
+int fastlec_es_load_aig(const void *bytes, size_t len, fastlec_es_circuit **out);
+
+/* As fastlec_es_load_aig, reading the file at path. */
+int fastlec_es_load_aig_file(const char *path, fastlec_es_circuit **out);
+
+/* Sizes of a loaded circuit. */
+int fastlec_es_info_get(const fastlec_es_circuit *c, fastlec_es_info *info);
+
+/* Exact simulation of one circuit over the option's word range (paper, Section 2.2 and
+ * Section 3.3).  opts may be NULL (defaults).  Blocks until *out is filled. */
+int fastlec_es_check(const fastlec_es_circuit *c, const fastlec_es_options *opts, fastlec_es_result *out);
+
+/* Exact simulation of k circuits of different sizes and input counts in one persistent
+ * interpreter launch (whole space each; the option's word range is ignored).  cs: k handles;
+ * out: k results.  Returns the first per-circuit error; per-circuit errors also appear as a
+ * negative verdict. */
+int fastlec_es_check_batch(const fastlec_es_circuit *const *cs, size_t k, const fastlec_es_options *opts,
+                           fastlec_es_result *out);
+
+/* Release a handle (NULL is allowed). */
+void fastlec_es_free(fastlec_es_circuit *c);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *fastlec_es_last_error(void);
+
+/* ---- serving: continuous batching ---------------------------------------- */
+typedef struct fastlec_es_server fastlec_es_server;
+
+typedef struct {
+    uint64_t submitted, completed, rejected, steps;
+    uint64_t active, queued;
+    uint64_t charge_in_use_bytes, budget_bytes, peak_charge_bytes;
+    double busy_ms;              /* summed device time of the step kernels */
+} fastlec_es_server_stats;
+
+/* Start a server on opts->device with a device-memory budget for admitted jobs.  A job's
+ * charge is peak_live_slots * min(W, chunk_words) * 8 bytes: its node-value slots for
+ * the 64-pattern words it has in flight.  The server allocates that much for each admitted
+ * job.  Jobs stay queued until their charge fits beside the jobs in flight. */
+int fastlec_es_server_create(const fastlec_es_options *opts, size_t budget_bytes, fastlec_es_server **out);
+
+/* Queue a job; never blocks.  The circuit must stay alive until the job is polled done.
+ * FASTLEC_REJECTED if its charge exceeds the whole budget. */
+int fastlec_es_server_submit(fastlec_es_server *s, const fastlec_es_circuit *c, uint64_t *ticket);
+
+/* 1 and *out filled when the job is done, 0 when not yet (wait = 0), or a negative status.
+ * wait != 0 blocks until done. */
+int fastlec_es_server_poll(fastlec_es_server *s, uint64_t ticket, fastlec_es_result *out, int wait);
+
+/* Counters since creation. */
+int fastlec_es_server_stats_get(fastlec_es_server *s, fastlec_es_server_stats *st);
+
+/* Stop the server thread and free its memory; pending jobs are dropped. */
+void fastlec_es_server_destroy(fastlec_es_server *s);
+
+/* ---- diagnostics (no GPU needed) ------------------------------------------ */
+
+/* Compile the specialized kernel of c for gfx950 with hipRTC (cached per circuit and by
+ * source hash) without running it.  waves_per_eu: occupancy target 1..8.  Outputs may be
+ * NULL: *compile_ms = compile time paid by this call (0 when cached), *code_bytes = size of
+ * the code object. */
+int fastlec_es_compile_specialized(const fastlec_es_circuit *c, int waves_per_eu, double *compile_ms,
+                                   size_t *code_bytes);
+
+/* Copy the specialized kernel's HIP source into buf (len bytes, NUL-terminated, truncated
+ * to fit) and return the length it needs including the NUL.  buf may be NULL. */
+size_t fastlec_es_specialized_source(const fastlec_es_circuit *c, int waves_per_eu, char *buf, size_t len);
+
+/* Replay the interpreter instruction stream planned with `bundle` (1, 4 or 8) on the host,
+ * with the kernels' bundle semantics, for the 32-pattern half-words hw .. hw+count-1
+ * (half-word h holds patterns 32h .. 32h+31, bit j = pattern 32h+j).  out: count host
+ * words of miter values.  Checks the plan's slot map first (FASTLEC_ERR_INVALID if broken). */
+int fastlec_es_host_replay(const fastlec_es_circuit *c, uint32_t bundle, uint64_t hw, uint64_t count,
+                           uint32_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FASTLEC_ES_H */

@@ -1,0 +1,299 @@
+// C ABI of the exact-simulation library.  No exception crosses this boundary:
+// every entry point catches, stores a thread-local message and returns a status.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+
+#include "runtime.hpp"
+
+using namespace fes;
+
+struct fastlec_es_circuit {
+    Circuit c;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+template <class F>
+int guarded(F&& f) {
+    try {
+        g_last_error.clear();
+        return f();
+    } catch (const Error& e) {
+        return fail(e.code, e.msg);
+    } catch (const std::bad_alloc&) {
+        return fail(FASTLEC_ERR_NOMEM, "host allocation failed");
+    } catch (const std::exception& e) {
+        return fail(FASTLEC_ERR_DEVICE, e.what());
+    } catch (...) {
+        return fail(FASTLEC_ERR_DEVICE, "unknown error");
+    }
+}
+
+fastlec_es_options defaults() {
+    fastlec_es_options o;
+    std::memset(&o, 0, sizeof(o));
+    return o;
+}
+
+uint64_t range_patterns(uint32_t n, const HwRange& r) {
+    if (n < 5) return 1ull << n;  // one half-word holds the whole space
+    return 32ull * (r.end - r.begin);
+}
+
+void fill_result(const Circuit& c, const HwRange& r, uint64_t best, fastlec_es_result* out) {
+    const uint32_t n = c.plan1.num_inputs;
+    out->reserved = 0;
+    out->plan_ms = c.plan_ms;
+    const uint64_t begin_p = n < 5 ? 0 : 32ull * r.begin;
+    const uint64_t words = n >= 6 ? (1ull << (n - 6)) : 1ull;
+    if (best == ~0ull) {
+        out->verdict = FASTLEC_EQUIVALENT;
+        out->cex = 0;
+        out->patterns_evaluated = range_patterns(n, r);
+        out->next_word = std::min(words, (r.end + 1) / 2);
+    } else {
+        out->verdict = FASTLEC_NONEQUIVALENT;
+        out->cex = best;
+        out->patterns_evaluated = best - begin_p + 1;
+        out->next_word = best / 64;
+    }
+}
+
+// Choose the kernel: the specialized one pays a compile (about a second) once per circuit,
+// so it is used when the space is large enough for that to be repaid.
+bool use_specialized(const Circuit& c, const fastlec_es_options& o, const HwRange& r) {
+    if (o.kernel == FASTLEC_KERNEL_SPECIALIZED) return true;
+    if (o.kernel != FASTLEC_KERNEL_AUTO) return false;
+    const double work = (double)c.plan1.num_gate_instrs * 32.0 * (double)(r.end - r.begin);
+    return work >= 1e12;
+}
+
+void check_one(Circuit& c, const fastlec_es_options& o, fastlec_es_result* out) {
+    if (o.kernel < FASTLEC_KERNEL_AUTO || o.kernel > FASTLEC_KERNEL_INTERP_HBM)
+        throw Error{kErrInvalid, "unknown kernel"};
+    Device& dev = device(o.device);
+    hipStream_t stream = o.hip_stream ? (hipStream_t)o.hip_stream : dev.stream;
+    HwRange full = range_of(c.plan1.num_inputs, o.begin_word, o.end_word);
+    std::memset(out, 0, sizeof(*out));
+    const bool spec = use_specialized(c, o, full);
+    std::shared_ptr<JitKernel> jk;
+    double compile_ms = 0;
+    if (spec) jk = jit_kernel(c, 2, &compile_ms);
+    Schedule sch;
+    if (!spec) {
+        std::vector<Circuit*> one{&c};
+        sch = default_schedule(dev, one, &o);
+        if (o.tile_words) sch.tile_hw = 2ull * o.tile_words;
+    }
+    // Without a deadline or cancel flag the whole range is one launch.  With one, the range
+    // runs as ascending chunks with the host checking between chunks.
+    const bool chunked = o.deadline_s > 0 || o.cancel_flag;
+    const double t_start = now_ms();
+    uint64_t chunk = full.end - full.begin;
+    if (chunked) chunk = std::max<uint64_t>(4096, (full.end - full.begin) / 256);
+    double kernel_ms = 0;
+    uint64_t best = ~0ull;
+    uint64_t done_to = full.begin;
+    int status = FASTLEC_OK;
+    for (uint64_t lo = full.begin; lo < full.end && best == ~0ull; lo += chunk) {
+        if (chunked) {
+            if (o.cancel_flag && *o.cancel_flag) { status = FASTLEC_CANCELLED; break; }
+            if (o.deadline_s > 0 && now_ms() - t_start >= o.deadline_s * 1e3) { status = FASTLEC_TIMEOUT; break; }
+        }
+        HwRange r{lo, std::min(full.end, lo + chunk)};
+        double ms = 0;
+        if (spec) {
+            run_jit(dev, c, *jk, r, o.tile_words ? 2ull * o.tile_words : 0, stream, nullptr, &best, &ms);
+        } else {
+            std::vector<Circuit*> one{&c};
+            std::vector<HwRange> rs{r};
+            std::vector<uint64_t> b;
+            run_interp(dev, one, rs, sch, stream, nullptr, b, &ms);
+            best = b[0];
+        }
+        kernel_ms += ms;
+        done_to = r.end;
+    }
+    if (status != FASTLEC_OK) {
+        out->verdict = status;
+        out->patterns_evaluated = c.plan1.num_inputs < 5 ? 0 : 32ull * (done_to - full.begin);
+        out->next_word = done_to / 2;
+        out->plan_ms = c.plan_ms;
+        out->kernel_ms = kernel_ms;
+        out->compile_ms = compile_ms;
+        throw Error{status, status == FASTLEC_CANCELLED ? "cancelled" : "deadline passed"};
+    }
+    fill_result(c, full, best, out);
+    out->kernel_ms = kernel_ms;
+    out->compile_ms = compile_ms;
+}
+
+}  // namespace
+
+extern "C" {
+
+void fastlec_es_options_init(fastlec_es_options* opts) {
+    if (opts) *opts = defaults();
+}
+
+const char* fastlec_es_last_error(void) { return g_last_error.c_str(); }
+
+int fastlec_es_load_aig(const void* bytes, size_t len, fastlec_es_circuit** out) {
+    return guarded([&] {
+        if (!out) throw Error{kErrInvalid, "null output handle"};
+        *out = nullptr;
+        auto h = std::make_unique<fastlec_es_circuit>();
+        h->c.aig = parse_aiger((const uint8_t*)bytes, len);
+        const double t0 = now_ms();
+        h->c.plan1 = make_plan(h->c.aig, Order::Auto, 1);
+        h->c.plan_ms = now_ms() - t0;
+        *out = h.release();
+        return FASTLEC_OK;
+    });
+}
+
+int fastlec_es_load_aig_file(const char* path, fastlec_es_circuit** out) {
+    return guarded([&] {
+        if (!path) throw Error{kErrInvalid, "null path"};
+        std::ifstream f(path, std::ios::binary);
+        if (!f) throw Error{kErrInvalid, std::string("cannot open ") + path};
+        std::stringstream ss;
+        ss << f.rdbuf();
+        std::string s = ss.str();
+        return fastlec_es_load_aig(s.data(), s.size(), out);
+    });
+}
+
+int fastlec_es_info_get(const fastlec_es_circuit* c, fastlec_es_info* info) {
+    return guarded([&] {
+        if (!c || !info) throw Error{kErrInvalid, "null argument"};
+        const Plan& p = c->c.plan1;
+        info->num_pis = p.num_inputs;
+        info->num_ands = p.num_ands_file;
+        info->num_ands_tfi = p.num_ands_tfi;
+        info->num_outputs = p.num_outputs;
+        info->peak_live_slots = p.peak_slots;
+        info->num_instrs = p.num_gate_instrs;
+        info->levels = p.levels;
+        info->reserved = 0;
+        return FASTLEC_OK;
+    });
+}
+
+int fastlec_es_check(const fastlec_es_circuit* c, const fastlec_es_options* opts, fastlec_es_result* out) {
+    return guarded([&] {
+        if (!c || !out) throw Error{kErrInvalid, "null argument"};
+        fastlec_es_options o = opts ? *opts : defaults();
+        check_one(const_cast<Circuit&>(c->c), o, out);
+        return FASTLEC_OK;
+    });
+}
+
+int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const fastlec_es_options* opts,
+                           fastlec_es_result* out) {
+    return guarded([&] {
+        if (!cs || !out) throw Error{kErrInvalid, "null argument"};
+        if (k == 0) return FASTLEC_OK;
+        fastlec_es_options o = opts ? *opts : defaults();
+        Device& dev = device(o.device);
+        hipStream_t stream = o.hip_stream ? (hipStream_t)o.hip_stream : dev.stream;
+        std::vector<Circuit*> v;
+        std::vector<HwRange> rs;
+        for (size_t i = 0; i < k; ++i) {
+            if (!cs[i]) throw Error{kErrInvalid, "null circuit in batch"};
+            v.push_back(const_cast<Circuit*>(&cs[i]->c));
+            rs.push_back(range_of(v.back()->plan1.num_inputs, 0, 0));
+        }
+        Schedule sch = default_schedule(dev, v, &o);
+        if (o.tile_words) sch.tile_hw = 2ull * o.tile_words;
+        std::vector<uint64_t> best;
+        double ms = 0;
+        run_interp(dev, v, rs, sch, stream, nullptr, best, &ms);
+        for (size_t i = 0; i < k; ++i) {
+            std::memset(&out[i], 0, sizeof(out[i]));
+            fill_result(*v[i], rs[i], best[i], &out[i]);
+            out[i].kernel_ms = ms;
+        }
+        return FASTLEC_OK;
+    });
+}
+
+void fastlec_es_free(fastlec_es_circuit* c) { delete c; }
+
+// Compile the specialized kernel of a circuit without running it (no GPU needed).
+// Writes the generated source's size and compile time; used to check the build path.
+int fastlec_es_compile_specialized(const fastlec_es_circuit* c, int waves_per_eu, double* compile_ms,
+                                   size_t* code_bytes) {
+    return guarded([&] {
+        if (!c) throw Error{kErrInvalid, "null circuit"};
+        if (waves_per_eu < 1 || waves_per_eu > 8) throw Error{kErrInvalid, "waves_per_eu must be 1..8"};
+        double ms = 0;
+        auto k = jit_kernel(const_cast<Circuit&>(c->c), waves_per_eu, &ms);
+        if (compile_ms) *compile_ms = ms;
+        if (code_bytes) *code_bytes = k->code.size();
+        return FASTLEC_OK;
+    });
+}
+
+// Text of the specialized kernel source (for inspection); returns the length needed.
+size_t fastlec_es_specialized_source(const fastlec_es_circuit* c, int waves_per_eu, char* buf, size_t len) {
+    if (!c) return 0;
+    std::string s = jit_source(c->c.plan1, waves_per_eu, 256);
+    if (buf && len) {
+        size_t m = std::min(len - 1, s.size());
+        std::memcpy(buf, s.data(), m);
+        buf[m] = 0;
+    }
+    return s.size() + 1;
+}
+
+// Replay of the interpreter instruction stream on the host (bundle semantics: all reads of a
+// bundle, then all writes), for validating plans without a GPU.  Returns the miter words of
+// the 32-pattern half-words [hw, hw + count) in out.
+int fastlec_es_host_replay(const fastlec_es_circuit* c, uint32_t bundle, uint64_t hw, uint64_t count, uint32_t* out) {
+    return guarded([&] {
+        if (!c || !out) throw Error{kErrInvalid, "null argument"};
+        Circuit& cc = const_cast<Circuit&>(c->c);
+        const Plan& p = cc.plan_for(bundle);
+        std::string err = validate_plan(cc.aig, p);
+        if (!err.empty()) throw Error{kErrInvalid, "invalid plan: " + err};
+        std::vector<uint32_t> rows(p.rows, 0);
+        for (uint64_t t = 0; t < count; ++t) {
+            const uint64_t h = hw + t;
+            static const uint32_t kc[5] = {0xAAAAAAAAu, 0xCCCCCCCCu, 0xF0F0F0F0u, 0xFF00FF00u, 0xFFFF0000u};
+            rows[0] = 0;
+            for (uint32_t i = 0; i < p.num_inputs; ++i)
+                rows[1 + i] = i < 5 ? kc[i] : 0u - (uint32_t)((h >> (i - 5)) & 1u);
+            uint32_t m = 0;
+            for (size_t b0 = 0; b0 < p.prog.size(); b0 += p.bundle) {
+                std::vector<uint32_t> val(p.bundle);
+                for (uint32_t u = 0; u < p.bundle; ++u) {
+                    const Instr& ins = p.prog[b0 + u];
+                    uint32_t a = rows[ins.a & kRowMask] ^ (0u - (ins.a >> 31));
+                    uint32_t b = rows[ins.b & kRowMask] ^ (0u - (ins.b >> 31));
+                    val[u] = a & b;
+                }
+                for (uint32_t u = 0; u < p.bundle; ++u) {
+                    const Instr& ins = p.prog[b0 + u];
+                    rows[ins.d] = val[u];
+                    if (ins.flags & kOutPos) m |= val[u];
+                    if (ins.flags & kOutNeg) m |= ~val[u];
+                }
+            }
+            out[t] = m;
+        }
+        return FASTLEC_OK;
+    });
+}
+
+}  // extern "C"

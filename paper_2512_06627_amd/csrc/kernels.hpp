@@ -1,0 +1,54 @@
+// Device-side data layouts shared by the host runtime and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "plan.hpp"
+
+namespace fes {
+
+// One circuit of an interpreter launch (plain check = a launch with one cone).
+// Pattern space unit: a 32-bit "half-word" h holds patterns 32h .. 32h+31; each lane
+// of a wave holds `K` half-words per value-file row.
+struct ConeDesc {
+    const Instr* prog;   // device copy of the instruction stream
+    uint32_t n_instr;    // multiple of the plan's bundle size
+    uint32_t n_inputs;
+    uint32_t rows;       // value-file rows this cone uses
+    uint32_t best_index; // index into the launch's best[] array
+    uint64_t hw_begin;   // half-word range [hw_begin, hw_end)
+    uint64_t hw_end;
+    uint64_t hw_first;   // hw_begin rounded down to the pass size (64 * K)
+    uint64_t tile_hw;    // half-words per work item (multiple of 64 * K)
+    uint64_t item_begin; // first work item of this cone in the launch
+    uint64_t item_end;   // one past its last work item
+};
+static_assert(sizeof(ConeDesc) == 72, "descriptor layout");
+
+// Control block at the start of each launch's device buffer.
+struct alignas(64) LaunchCtl {
+    unsigned long long next_item;  // work-claim counter
+    unsigned long long pad[7];
+};
+
+struct InterpLaunch {
+    const ConeDesc* cones;
+    uint32_t num_cones;
+    uint32_t rows_max;        // value-file rows per wave
+    uint64_t total_items;
+    LaunchCtl* ctl;
+    unsigned long long* best; // per cone: lowest failing pattern, ~0 = none yet
+    uint32_t* hbm_rows;       // device value files (HBM tier); null for the LDS tier
+    const int* cancel;        // device-visible flag polled per work item, may be null
+};
+
+// Launch the interpreter.  K = half-words per lane per row (1, 2, 4); B = bundle size
+// (1, 4, 8); lds = value file in LDS (else in hbm_rows).  Returns hipSuccess or an error.
+hipError_t launch_interp(const InterpLaunch& L, int K, int B, bool lds, int grid, int block,
+                         hipStream_t stream);
+
+// Largest per-workgroup dynamic LDS the interpreter may request.
+size_t interp_lds_bytes(uint32_t rows, int K, int waves_per_block);
+
+}  // namespace fes

@@ -1,0 +1,297 @@
+#include "runtime.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <numeric>
+
+namespace fes {
+
+[[noreturn]] void throw_hip(hipError_t e, const char* what) {
+    throw Error{kErrDevice, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+bool trace_on() {
+    static const bool on = [] {
+        const char* v = std::getenv("FASTLEC_ES_TRACE");
+        return v && *v && *v != '0';
+    }();
+    return on;
+}
+
+void trace(const char* fmt, ...) {
+    if (!trace_on()) return;
+    va_list ap;
+    va_start(ap, fmt);
+    std::fprintf(stderr, "[fastlec_es %.1f ms] ", now_ms());
+    std::vfprintf(stderr, fmt, ap);
+    std::fputc('\n', stderr);
+    std::fflush(stderr);
+    va_end(ap);
+}
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// ---- circuits --------------------------------------------------------------
+
+Circuit::~Circuit() {
+    for (auto& kv : dev_prog) {
+        if (!kv.second) continue;
+        int cur = 0;
+        if (hipGetDevice(&cur) == hipSuccess && hipSetDevice(kv.first.first) == hipSuccess) {
+            (void)hipFree(kv.second);
+            (void)hipSetDevice(cur);
+        }
+    }
+    for (auto& kv : jit) {
+        for (auto& dm : kv.second->per_device) {
+            int cur = 0;
+            if (hipGetDevice(&cur) == hipSuccess && hipSetDevice(dm.first) == hipSuccess) {
+                (void)hipModuleUnload(dm.second.first);
+                (void)hipSetDevice(cur);
+            }
+        }
+    }
+}
+
+const Plan& Circuit::plan_for(uint32_t bundle) {
+    if (bundle <= 1) return plan1;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = bundled.find(bundle);
+    if (it == bundled.end()) it = bundled.emplace(bundle, std::make_unique<Plan>(make_plan(aig, Order::Auto, bundle))).first;
+    return *it->second;
+}
+
+const Instr* Circuit::device_prog(int dev, uint32_t bundle, hipStream_t s) {
+    const Plan& p = plan_for(bundle);
+    std::lock_guard<std::mutex> g(mu);
+    auto key = std::make_pair(dev, bundle);
+    auto it = dev_prog.find(key);
+    if (it != dev_prog.end()) return it->second;
+    Instr* d = nullptr;
+    FES_HIP(hipMalloc(&d, std::max<size_t>(p.prog.size(), 1) * sizeof(Instr)));
+    if (!p.prog.empty()) {
+        FES_HIP(hipMemcpyAsync(d, p.prog.data(), p.prog.size() * sizeof(Instr), hipMemcpyHostToDevice, s));
+        FES_HIP(hipStreamSynchronize(s));
+    }
+    dev_prog[key] = d;
+    return d;
+}
+
+// ---- devices ----------------------------------------------------------------
+
+Buffer Device::acquire(size_t bytes) {
+    bytes = (bytes + 4095) & ~size_t(4095);
+    {
+        std::lock_guard<std::mutex> g(mu);
+        size_t best = SIZE_MAX;
+        for (size_t i = 0; i < free_bufs.size(); ++i)
+            if (free_bufs[i].bytes >= bytes && (best == SIZE_MAX || free_bufs[i].bytes < free_bufs[best].bytes)) best = i;
+        if (best != SIZE_MAX) {
+            Buffer b = free_bufs[best];
+            free_bufs.erase(free_bufs.begin() + best);
+            return b;
+        }
+    }
+    Buffer b;
+    b.bytes = bytes;
+    if (hipMalloc(&b.dev, bytes) != hipSuccess) throw Error{kErrNoMem, "device allocation failed"};
+    if (hipHostMalloc(&b.host, bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipFree(b.dev);
+        throw Error{kErrNoMem, "pinned host allocation failed"};
+    }
+    return b;
+}
+
+void Device::release(Buffer b) {
+    std::lock_guard<std::mutex> g(mu);
+    free_bufs.push_back(b);
+}
+
+Device& device(int ordinal) {
+    static std::mutex mu;
+    static std::map<int, std::unique_ptr<Device>> devs;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = devs.find(ordinal);
+    if (it != devs.end()) {
+        FES_HIP(hipSetDevice(ordinal));
+        return *it->second;
+    }
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count == 0) throw Error{kErrDevice, "no HIP device"};
+    if (ordinal < 0 || ordinal >= count) throw Error{kErrInvalid, "device ordinal out of range"};
+    trace("device %d: first use, %d devices", ordinal, count);
+    auto d = std::make_unique<Device>();
+    d->ordinal = ordinal;
+    FES_HIP(hipSetDevice(ordinal));
+    FES_HIP(hipGetDeviceProperties(&d->prop, ordinal));
+    if (std::strncmp(d->prop.gcnArchName, "gfx950", 6) != 0)
+        throw Error{kErrDevice, std::string("built for gfx950, device is ") + d->prop.gcnArchName};
+    FES_HIP(hipStreamCreateWithFlags(&d->stream, hipStreamNonBlocking));
+    trace("device %d: %s, %d CUs, LDS %zu per block / %zu per CU", ordinal, d->prop.gcnArchName,
+          d->prop.multiProcessorCount, (size_t)d->prop.sharedMemPerBlock, (size_t)d->prop.maxSharedMemoryPerMultiProcessor);
+    Device& ref = *d;
+    devs[ordinal] = std::move(d);
+    return ref;
+}
+
+HwRange range_of(uint32_t n, uint64_t begin_word, uint64_t end_word) {
+    const uint64_t words = n >= 6 ? (1ull << (n - 6)) : 1ull;
+    const uint64_t halfs = n >= 5 ? (1ull << (n - 5)) : 1ull;
+    if (begin_word == 0 && end_word == 0) end_word = words;
+    if (begin_word >= end_word || end_word > words) throw Error{kErrInvalid, "word range empty or beyond 2^(n-6) words"};
+    return HwRange{std::min(2 * begin_word, halfs), std::min(2 * end_word, halfs)};
+}
+
+// ---- interpreter launches ------------------------------------------------------
+
+namespace {
+
+struct Layout {
+    size_t best_off, desc_off, files_off, total;
+};
+
+Layout layout(size_t k, size_t file_bytes) {
+    Layout l;
+    l.best_off = sizeof(LaunchCtl);
+    l.desc_off = (l.best_off + 8 * k + 63) & ~size_t(63);
+    l.files_off = (l.desc_off + sizeof(ConeDesc) * k + 255) & ~size_t(255);
+    l.total = l.files_off + file_bytes;
+    return l;
+}
+
+int max_waves_per_cu(const Device& d) { return 32; }
+
+}  // namespace
+
+Schedule default_schedule(Device& dev, const std::vector<Circuit*>& cs, const fastlec_es_options* o) {
+    Schedule s;
+    if (o && o->words_per_thread) s.K = (int)o->words_per_thread;
+    if (o && o->wg_size) s.block = (int)o->wg_size;
+    if (o && o->kernel == FASTLEC_KERNEL_INTERP_HBM) s.lds = false;
+    if (s.K != 1 && s.K != 2 && s.K != 4) throw Error{kErrInvalid, "words_per_thread must be 1, 2 or 4"};
+    if (s.block < 64 || s.block > 1024 || s.block % 64) throw Error{kErrInvalid, "wg_size must be a multiple of 64 in [64, 1024]"};
+    uint32_t rows = 0;
+    for (Circuit* c : cs) rows = std::max(rows, c->plan_for(s.B).rows);
+    const size_t lds_cu = dev.prop.maxSharedMemoryPerMultiProcessor ? dev.prop.maxSharedMemoryPerMultiProcessor : 65536;
+    const size_t lds_blk = dev.prop.sharedMemPerBlock ? dev.prop.sharedMemPerBlock : 65536;
+    if (s.lds) {
+        // Shrink K, then the workgroup, until at least one workgroup fits; else use HBM rows.
+        while (s.lds && interp_lds_bytes(rows, s.K, s.block / 64) > lds_blk) {
+            if (!(o && o->wg_size) && s.block > 64) s.block /= 2;
+            else if (!(o && o->words_per_thread) && s.K > 1) s.K /= 2;
+            else s.lds = false;
+        }
+    }
+    const int waves_per_block = s.block / 64;
+    int blocks_per_cu;
+    if (s.lds) {
+        blocks_per_cu = (int)(lds_cu / interp_lds_bytes(rows, s.K, waves_per_block));
+        blocks_per_cu = std::max(1, std::min(blocks_per_cu, max_waves_per_cu(dev) / waves_per_block));
+    } else {
+        blocks_per_cu = std::max(1, 16 / waves_per_block);
+    }
+    s.grid = dev.prop.multiProcessorCount * blocks_per_cu;
+    return s;
+}
+
+void run_interp(Device& dev, const std::vector<Circuit*>& cs, const std::vector<HwRange>& ranges, const Schedule& sch,
+                hipStream_t stream, const int* cancel, std::vector<uint64_t>& best, double* kernel_ms) {
+    const size_t k = cs.size();
+    const uint32_t pass_hw = 64u * (uint32_t)sch.K;
+    uint32_t rows_max = 0;
+    for (Circuit* c : cs) rows_max = std::max(rows_max, c->plan_for(sch.B).rows);
+    const size_t waves = (size_t)sch.grid * (sch.block / 64);
+    const size_t file_bytes = sch.lds ? 0 : waves * rows_max * 64ull * sch.K * 4ull;
+    Layout lay = layout(k, file_bytes);
+    Buffer buf = dev.acquire(lay.total);
+    struct Releaser {
+        Device& d;
+        Buffer b;
+        ~Releaser() { d.release(b); }
+    } rel{dev, buf};
+
+    // Longest-processing-time order: cones with the most gate evaluations get the lowest
+    // item numbers, so the big ones start first and the small ones fill the tail.
+    std::vector<size_t> order(k);
+    std::iota(order.begin(), order.end(), 0);
+    std::vector<double> cost(k);
+    for (size_t i = 0; i < k; ++i)
+        cost[i] = (double)cs[i]->plan_for(sch.B).prog.size() * (double)(ranges[i].end - ranges[i].begin);
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+
+    uint8_t* host = (uint8_t*)buf.host;
+    std::memset(host, 0, lay.files_off);
+    uint64_t* hbest = (uint64_t*)(host + lay.best_off);
+    ConeDesc* hdesc = (ConeDesc*)(host + lay.desc_off);
+    uint64_t item = 0;
+    for (size_t t = 0; t < k; ++t) {
+        size_t i = order[t];
+        Circuit* c = cs[i];
+        const Plan& p = c->plan_for(sch.B);
+        ConeDesc& d = hdesc[t];
+        d.prog = c->device_prog(dev.ordinal, sch.B, stream);
+        d.n_instr = (uint32_t)p.prog.size();
+        d.n_inputs = p.num_inputs;
+        d.rows = p.rows;
+        d.best_index = (uint32_t)i;
+        d.hw_begin = ranges[i].begin;
+        d.hw_end = ranges[i].end;
+        d.hw_first = ranges[i].begin / pass_hw * pass_hw;
+        uint64_t span = d.hw_end - d.hw_first;
+        uint64_t tile = sch.tile_hw;
+        if (!tile) {  // about 16 work items per wave over the launch, within [1, 64] passes
+            uint64_t target = span / std::max<uint64_t>(1, waves * 16);
+            tile = pass_hw;
+            while (tile < target && tile < 64ull * pass_hw) tile *= 2;
+        }
+        tile = (tile + pass_hw - 1) / pass_hw * pass_hw;
+        d.tile_hw = tile;
+        d.item_begin = item;
+        item += (span + tile - 1) / tile;
+        d.item_end = item;
+        hbest[i] = ~0ull;
+    }
+    uint8_t* devp = (uint8_t*)buf.dev;
+    InterpLaunch L;
+    L.cones = (const ConeDesc*)(devp + lay.desc_off);
+    L.num_cones = (uint32_t)k;
+    L.rows_max = rows_max;
+    L.total_items = item;
+    L.ctl = (LaunchCtl*)devp;
+    L.best = (unsigned long long*)(devp + lay.best_off);
+    L.hbm_rows = sch.lds ? nullptr : (uint32_t*)(devp + lay.files_off);
+    L.cancel = cancel;
+
+    hipEvent_t e0, e1;
+    FES_HIP(hipEventCreate(&e0));
+    FES_HIP(hipEventCreate(&e1));
+    struct Ev {
+        hipEvent_t a, b;
+        ~Ev() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } ev{e0, e1};
+    trace("interp launch: %zu cones, %llu items, K=%d B=%d %s grid=%d block=%d rows=%u", k,
+          (unsigned long long)item, sch.K, sch.B, sch.lds ? "lds" : "hbm", sch.grid, sch.block, rows_max);
+    FES_HIP(hipMemcpyAsync(devp, host, lay.files_off, hipMemcpyHostToDevice, stream));
+    FES_HIP(hipEventRecord(e0, stream));
+    FES_HIP(launch_interp(L, sch.K, sch.B, sch.lds, sch.grid, sch.block, stream));
+    FES_HIP(hipEventRecord(e1, stream));
+    FES_HIP(hipMemcpyAsync(hbest, devp + lay.best_off, 8 * k, hipMemcpyDeviceToHost, stream));
+    FES_HIP(hipStreamSynchronize(stream));
+    trace("interp done");
+    float ms = 0;
+    FES_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (kernel_ms) *kernel_ms = ms;
+    best.assign(hbest, hbest + k);
+}
+
+}  // namespace fes

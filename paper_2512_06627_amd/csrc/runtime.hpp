@@ -1,0 +1,112 @@
+// Host runtime: circuits, per-device state, schedules and launches.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/fastlec_es.h"
+#include "aig.hpp"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+namespace fes {
+
+[[noreturn]] void throw_hip(hipError_t e, const char* what);
+#define FES_HIP(call)                                  \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess) ::fes::throw_hip(e_, #call); \
+    } while (0)
+
+double now_ms();
+
+// Opt-in trace of host phases to stderr (environment FASTLEC_ES_TRACE=1).
+bool trace_on();
+void trace(const char* fmt, ...);
+
+// A straight-line kernel compiled for one circuit (hipRTC code object) and its
+// per-device module handles.
+struct JitKernel {
+    std::string source;
+    std::vector<char> code;  // code object
+    uint64_t hash = 0;
+    int waves_per_eu = 2;
+    int block = 256;
+    double compile_ms = 0;
+    std::mutex mu;
+    std::map<int, std::pair<hipModule_t, hipFunction_t>> per_device;
+    std::map<int, int> blocks_per_cu;
+};
+
+struct Circuit {
+    Aig aig;
+    Plan plan1;  // sequential plan (specialized kernel, info)
+    double plan_ms = 0;
+    std::mutex mu;
+    std::map<uint32_t, std::unique_ptr<Plan>> bundled;                  // bundle size -> plan
+    std::map<std::pair<int, uint32_t>, Instr*> dev_prog;                  // (device, bundle) -> stream
+    std::map<int, std::shared_ptr<JitKernel>> jit;                       // waves_per_eu -> kernel
+    ~Circuit();
+    const Plan& plan_for(uint32_t bundle);
+    const Instr* device_prog(int device, uint32_t bundle, hipStream_t s);
+};
+
+// Device buffers handed out per call (thread-safe pool).
+struct Buffer {
+    void* dev = nullptr;
+    void* host = nullptr;  // pinned, same size
+    size_t bytes = 0;
+};
+
+struct Device {
+    int ordinal = 0;
+    hipDeviceProp_t prop{};
+    hipStream_t stream = nullptr;  // library stream
+    std::mutex mu;
+    std::vector<Buffer> free_bufs;
+    Buffer acquire(size_t bytes);
+    void release(Buffer b);
+};
+Device& device(int ordinal);
+
+// Interpreter schedule: K half-words per lane, bundle B, workgroup size, tile size, tier.
+struct Schedule {
+    int K = 2;
+    int B = 8;
+    int block = 256;
+    uint64_t tile_hw = 0;  // 0 = derived
+    bool lds = true;
+    int grid = 0;          // 0 = derived (persistent: fill the chip)
+};
+
+struct CheckOut {
+    uint64_t best = ~0ull;
+    double kernel_ms = 0;
+    double compile_ms = 0;
+};
+
+// Range of a check in half-words (32 patterns).
+struct HwRange {
+    uint64_t begin, end;
+};
+HwRange range_of(uint32_t n, uint64_t begin_word, uint64_t end_word);
+
+// One interpreter launch over several cones (k = 1 for a plain check).
+void run_interp(Device& dev, const std::vector<Circuit*>& cs, const std::vector<HwRange>& ranges,
+                const Schedule& sch, hipStream_t stream, const int* cancel, std::vector<uint64_t>& best,
+                double* kernel_ms);
+
+Schedule default_schedule(Device& dev, const std::vector<Circuit*>& cs, const fastlec_es_options* o);
+
+// Specialized kernel.
+std::shared_ptr<JitKernel> jit_kernel(Circuit& c, int waves_per_eu, double* compile_ms);
+void run_jit(Device& dev, Circuit& c, JitKernel& k, const HwRange& r, uint64_t tile_hw, hipStream_t stream,
+             const int* cancel, uint64_t* best, double* kernel_ms);
+std::string jit_source(const Plan& p, int waves_per_eu, int block);
+
+}  // namespace fes

@@ -1,0 +1,173 @@
+"""GPU parity: the HIP exact-simulation path against the oracle, bit for bit.
+
+Every expected value comes from the oracle (directly, or from
+tests/golden/expected.json, written by tests/golden/make_expected.py with the
+oracle only) or from the hand-worked fixtures.  The answer compared is the
+verdict and the lowest failing pattern, which are unique.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import miters
+import oracle
+import paper_2512_06627_amd as es
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+KERNELS = ["interp", "interp_hbm", "specialized"]
+
+
+def expected(name):
+    return json.load(open(os.path.join(GOLDEN, "expected.json")))[name]["lowest_failure"]
+
+
+def gpu_answer(circ, **kw):
+    r = es.fastlec_es_check(circ, **kw)
+    if r["verdict"] == es.FASTLEC_EQUIVALENT:
+        return None
+    assert r["verdict"] == es.FASTLEC_NONEQUIVALENT
+    return r["cex"]
+
+
+def hand_cases():
+    spec = json.load(open(os.path.join(GOLDEN, "hand_worked.json")))
+    return [(k, v) for k, v in spec.items() if not k.startswith("_")]
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("name,spec", hand_cases(), ids=[k for k, _ in hand_cases()])
+def test_hand_worked(name, spec, kernel):
+    data = open(os.path.join(GOLDEN, "hand", name), "rb").read()
+    if "error" in spec:
+        with pytest.raises(es.EsError) as ei:
+            es.fastlec_es_load_aig(data)
+        assert ei.value.code == {"parse": es.FASTLEC_ERR_PARSE, "unsupported": es.FASTLEC_ERR_UNSUPPORTED}[spec["error"]]
+        return
+    c = es.fastlec_es_load_aig(data)
+    r = es.fastlec_es_check(c, kernel=kernel)
+    assert gpu_answer(c, kernel=kernel) == spec["expect"]
+    if spec["expect"] is None:
+        n = c.info()["num_pis"]
+        assert r["patterns_evaluated"] == 1 << n  # cost_ES = 2^num_PIs
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("name", ["mult6_array_wallace", "mult6_array_wallace_f1", "mult12_array_booth",
+                                  "mult12_array_booth_f1", "mult12_array_booth_f2", "mult12_array_booth_f3",
+                                  "mult12_array_booth_f4"])
+def test_workloads_match_oracle_golden(name, kernel):
+    g = miters.workload(name)
+    for data in (g.to_aag(), g.to_aig()):
+        c = es.fastlec_es_load_aig(data)
+        assert gpu_answer(c, kernel=kernel) == expected(name)
+
+
+@pytest.mark.parametrize("name", ["mult16_array_booth_f1", "mult16_array_booth_f2", "mult16_array_booth_f3",
+                                  "mult16_array_booth_f4", "mac8_fused_separate_f1"])
+def test_full_size_faults_match_oracle_golden(name):
+    exp = expected(name)
+    c = es.fastlec_es_load_aig(miters.workload(name).to_aig())
+    for kernel in ("specialized", "interp"):
+        assert gpu_answer(c, kernel=kernel) == exp
+
+
+def _minterm_cases():
+    cases = []
+    for n in (1, 3, 5, 6, 7, 11, 12, 13, 17):
+        top = (1 << n) - 1
+        for t in sorted({0, 1, 31, 32, 63, 64, 2047, 2048, 4095, 4096, 65535, 65536, top // 2, top - 1, top}):
+            if t <= top:
+                cases.append((n, (t,)))
+    cases += [(20, (999_999, 1 << 19)), (20, (5, 1048575)), (16, (40000, 40001, 39999))]
+    return cases
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("n,targets", _minterm_cases())
+def test_minterm_edges(n, targets, kernel):
+    """A minterm circuit fails exactly at its targets: lowest = min (lane, wave, tile and word edges)."""
+    c = es.fastlec_es_load_aig(miters.minterm_miter(n, targets).to_aag())
+    assert gpu_answer(c, kernel=kernel) == min(targets)
+
+
+@pytest.mark.parametrize("K", [1, 2, 4])
+@pytest.mark.parametrize("wg", [64, 256])
+@pytest.mark.parametrize("tile_words", [0, 32, 1024])
+def test_schedule_invariance(K, wg, tile_words):
+    for name in ("mult12_array_booth_f2", "mult12_array_booth_f3"):
+        c = es.fastlec_es_load_aig(miters.workload(name).to_aig())
+        for kernel in ("interp", "interp_hbm"):
+            assert gpu_answer(c, kernel=kernel, words_per_thread=K, wg_size=wg, tile_words=tile_words) == expected(name)
+
+
+def test_word_ranges_resume():
+    """Checking [0, a) then [a, W) gives the same answer as one call (resume support)."""
+    name = "mult12_array_booth_f1"
+    exp = expected(name)
+    c = es.fastlec_es_load_aig(miters.workload(name).to_aig())
+    W = 1 << 18
+    for kernel in KERNELS:
+        for a in (1, exp // 64, exp // 64 + 1, W // 2):
+            r1 = es.fastlec_es_check(c, kernel=kernel, begin_word=0, end_word=a)
+            r2 = es.fastlec_es_check(c, kernel=kernel, begin_word=a, end_word=W)
+            first = r1["cex"] if r1["verdict"] else (r2["cex"] if r2["verdict"] else None)
+            assert first == exp
+            if r1["verdict"] == es.FASTLEC_EQUIVALENT:
+                assert r1["patterns_evaluated"] == 64 * a and r1["next_word"] == a
+
+
+def test_equivalent_range_counts():
+    c = es.fastlec_es_load_aig(miters.workload("mult12_array_booth").to_aig())
+    for kernel in KERNELS:
+        r = es.fastlec_es_check(c, kernel=kernel)
+        assert r["verdict"] == es.FASTLEC_EQUIVALENT and r["patterns_evaluated"] == 1 << 24
+        assert r["next_word"] == 1 << 18
+
+
+def test_repeated_runs_deterministic():
+    c = es.fastlec_es_load_aig(miters.workload("mult12_array_booth_f4").to_aig())
+    got = {gpu_answer(c, kernel=k) for k in KERNELS for _ in range(3)}
+    assert got == {expected("mult12_array_booth_f4")}
+
+
+def test_layered_cones_vs_oracle():
+    rng = miters.SplitMix64(77)
+    for i in range(8):
+        n = rng.between(8, 16)
+        fault = rng.between(1, 100) if i % 2 else None
+        g = miters.layered_cone_miter(1000 + i, n, rng.between(200, 1500), fault_seed=fault)
+        want = oracle.check(g.to_aag(), threads=8)
+        c = es.fastlec_es_load_aig(g.to_aig())
+        for kernel in KERNELS:
+            assert gpu_answer(c, kernel=kernel) == want
+
+
+def test_batch_matches_single():
+    rng = miters.SplitMix64(5)
+    circs, want = [], []
+    for i in range(24):
+        n = rng.between(6, 18)
+        fault = rng.between(1, 50) if i % 3 == 0 else None
+        g = miters.layered_cone_miter(2000 + i, n, rng.between(100, 1200), fault_seed=fault)
+        circs.append(es.fastlec_es_load_aig(g.to_aig()))
+        want.append(oracle.check(g.to_aag(), threads=8))
+    res = es.fastlec_es_check_batch(circs)
+    got = [r["cex"] if r["verdict"] else None for r in res]
+    assert got == want
+    # any permutation of the batch gives the same per-circuit answers
+    perm = list(range(len(circs)))[::-1]
+    res2 = es.fastlec_es_check_batch([circs[i] for i in perm])
+    assert [r["cex"] if r["verdict"] else None for r in res2] == [want[i] for i in perm]
+
+
+def test_invalid_ranges_rejected():
+    c = es.fastlec_es_load_aig(miters.minterm_miter(10, [3]).to_aag())
+    with pytest.raises(es.EsError) as ei:
+        es.fastlec_es_check(c, begin_word=5, end_word=5)
+    assert ei.value.code == es.FASTLEC_ERR_INVALID
+    with pytest.raises(es.EsError):
+        es.fastlec_es_check(c, begin_word=0, end_word=1 << 10)
