@@ -48,6 +48,101 @@ def cpu_baseline(aag: bytes, num_ands: int, target_s: float = 12.0):
             "sample": f"patterns [0, {patterns}) of the same miter, {dt:.1f} s on {threads} threads"}
 
 
+def batch_leg(es, stream, seed: int = 4, count: int = 256, faulty: int = 26):
+    """256 XOR-dense layered cones (n ~ U{18..30}, ~U[200, 5000] AND gates, 26 faulty):
+    one persistent batched launch (autotuned, hipGraph) vs one plain check per cone."""
+    import miters
+    rng = miters.SplitMix64(seed)
+    bad = set()
+    while len(bad) < faulty:
+        bad.add(rng.below(count))
+    t0 = time.perf_counter()
+    cones, work = [], 0
+    for i in range(count):
+        n, size = rng.between(18, 30), rng.between(200, 5000)
+        fault = rng.between(1, 1 << 20) if i in bad else None
+        c = es.fastlec_es_load_aig(miters.layered_cone_miter(seed * 100000 + i, n, size, fault_seed=fault).to_aig())
+        cones.append(c)
+        info = c.info()
+        work += info["num_ands_tfi"] * (1 << info["num_pis"])
+    gen_s = time.perf_counter() - t0
+
+    def answers(rs):
+        return [r["cex"] if r["verdict"] == es.FASTLEC_NONEQUIVALENT else None for r in rs]
+
+    plain = answers([es.fastlec_es_check(c, stream=stream, kernel="interp") for c in cones])  # warm: uploads
+    t0 = time.perf_counter()
+    plain2 = answers([es.fastlec_es_check(c, stream=stream, kernel="interp") for c in cones])
+    t_plain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    first = answers(es.fastlec_es_check_batch(cones, stream=stream))  # autotune + graph capture
+    t_first = time.perf_counter() - t0
+    reps = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        got = answers(es.fastlec_es_check_batch(cones, stream=stream))
+        reps.append(time.perf_counter() - t0)
+    t_batch = sorted(reps)[1]
+    return {"cones": count, "faulty_injected": faulty, "found_nonequivalent": sum(a is not None for a in got),
+            "node_patterns_upper_bound": work, "plain_cones_per_s": count / t_plain,
+            "batched_cones_per_s": count / t_batch, "batched_vs_plain_speedup": t_plain / t_batch,
+            "identical_verdicts": plain == plain2 == first == got, "first_batch_call_s": t_first,
+            "generate_s": gen_s}
+
+
+def serve_leg(es, stream, rate_hint: float, seed: int = 5, seconds: float = 30.0, max_requests: int = 400,
+              pool: int = 40, budget_gib: int = 64):
+    """Poisson stream of cones (n ~ U{16..34}, ~U[500, 20000] AND gates, 10% faulty) served by
+    continuous batching with an HBM budget; arrival rate set to 0.7 of the capacity implied by
+    `rate_hint` (node*patterns/s).  Reports p50/p99 latency and checks every answer against the
+    same cone checked alone."""
+    import miters
+    rng = miters.SplitMix64(seed)
+    t0 = time.perf_counter()
+    circs, works = [], []
+    for i in range(pool):
+        n, size = rng.between(16, 34), rng.between(500, 20000)
+        fault = rng.between(1, 1 << 20) if rng.below(10) == 0 else None
+        c = es.fastlec_es_load_aig(miters.layered_cone_miter(seed * 100000 + i, n, size, fault_seed=fault).to_aig())
+        info = c.info()
+        circs.append(c)
+        works.append(info["num_instrs"] * (1 << info["num_pis"]))
+    gen_s = time.perf_counter() - t0
+    mean_service = (sum(works) / len(works)) / rate_hint
+    lam = 0.7 / mean_service
+    srv = es.Server(budget_gib << 30, stream=None)
+    arrivals, tickets, which = [], [], []
+    start = time.perf_counter()
+    t_next = 0.0
+    while len(tickets) < max_requests and t_next < seconds:
+        now = time.perf_counter() - start
+        if now < t_next:
+            time.sleep(min(0.05, t_next - now))
+            continue
+        k = rng.below(pool)
+        tickets.append(srv.submit(circs[k]))
+        which.append(k)
+        t_next += rng.exponential(lam)
+    results = [srv.poll(t, wait=True) for t in tickets]
+    wall = time.perf_counter() - start
+    st = srv.stats()
+    srv.close()
+    alone = {}
+    for k in sorted(set(which)):
+        r = es.fastlec_es_check(circs[k], stream=stream, kernel="interp")
+        alone[k] = r["cex"] if r["verdict"] == es.FASTLEC_NONEQUIVALENT else None
+    served = [r["cex"] if r["verdict"] == es.FASTLEC_NONEQUIVALENT else None for r in results]
+    lat = sorted(r["latency_ms"] for r in results)
+    q = lambda f: lat[min(len(lat) - 1, int(f * len(lat)))]
+    done_work = sum(works[k] for k in which)
+    return {"requests": len(tickets), "arrival_rate_per_s": lam, "offered_load": 0.7, "wall_s": wall,
+            "latency_ms_p50": q(0.50), "latency_ms_p99": q(0.99), "requests_per_s": len(tickets) / wall,
+            "node_patterns_per_s": done_work / wall, "max_jobs_in_flight": st["max_active"],
+            "peak_charge_bytes": st["peak_charge_bytes"], "budget_bytes": st["budget_bytes"],
+            "server_device_bytes": st["device_bytes"], "steps": st["steps"],
+            "each_equal_alone": served == [alone[k] for k in which], "pool": pool, "generate_s": gen_s}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -56,6 +151,10 @@ def main():
     ap.add_argument("--kernel", default="specialized")
     ap.add_argument("--workload", default="mult16_array_booth")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the MAC, batch and serving legs")
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB (HBM counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only: exact simulation here is a single-GPU build "
@@ -68,6 +167,12 @@ def main():
 
     torch.cuda.init()
     stream = torch.cuda.current_stream()
+    if a.copy_calibration_mib:
+        src = torch.empty(a.copy_calibration_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     g = miters.workload(a.workload)
     aig = g.to_aig()
     t0 = time.perf_counter()
@@ -125,6 +230,20 @@ def main():
     }
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g.to_aag(), N)
+    if not a.no_secondary:
+        sec = {}
+        mac = es.fastlec_es_load_aig(miters.workload("mac8_fused_separate").to_aig())
+        es.fastlec_es_check(mac, stream=stream, kernel=a.kernel)
+        r = es.fastlec_es_check(mac, stream=stream, kernel=a.kernel)
+        mi = mac.info()
+        sec["mac8"] = {"kernel_ms": r["kernel_ms"], "equivalent": r["verdict"] == es.FASTLEC_EQUIVALENT,
+                       "node_patterns_per_s": mi["num_ands_tfi"] * (1 << mi["num_pis"]) / (r["kernel_ms"] / 1e3)}
+        print(json.dumps({"progress": "mac8", **sec["mac8"]}), file=sys.stderr, flush=True)
+        sec["batch"] = batch_leg(es, stream)
+        print(json.dumps({"progress": "batch", **sec["batch"]}), file=sys.stderr, flush=True)
+        interp_rate = sec["batch"]["node_patterns_upper_bound"] / (256 / sec["batch"]["batched_cones_per_s"])
+        sec["serve"] = serve_leg(es, stream, rate_hint=interp_rate, seconds=a.serve_seconds)
+        out["secondary"] = sec
     print(json.dumps(out), flush=True)
 
 

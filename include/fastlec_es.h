@@ -95,7 +95,9 @@ typedef struct {
     uint64_t next_word;          /* resume point: first word not known to be clean */
     double plan_ms;              /* host planning time (at load) */
     double compile_ms;           /* specialized-kernel compile time paid by this call (0 if cached) */
-    double kernel_ms;            /* device time of the simulation kernel */
+    double kernel_ms;            /* device time of the simulation kernel(s) */
+    double queued_ms;            /* server: admission - submission (host steady clock); 0 otherwise */
+    double latency_ms;           /* server: completion - submission (host steady clock); 0 otherwise */
 } fastlec_es_result;
 
 /* Fill *opts with defaults: device 0, library stream, tuned schedule, whole space. */
@@ -136,15 +138,23 @@ typedef struct fastlec_es_server fastlec_es_server;
 
 typedef struct {
     uint64_t submitted, completed, rejected, steps;
-    uint64_t active, queued;
+    uint64_t active, queued;             /* jobs in flight / waiting now */
     uint64_t charge_in_use_bytes, budget_bytes, peak_charge_bytes;
-    double busy_ms;              /* summed device time of the step kernels */
+    uint64_t device_bytes;               /* device memory the server actually holds (tables, value files) */
+    uint64_t max_active;                 /* most jobs in flight at once so far */
+    double busy_ms;                      /* summed device time of the step kernels */
 } fastlec_es_server_stats;
 
-/* Start a server on opts->device with a device-memory budget for admitted jobs.  A job's
- * charge is peak_live_slots * min(W, chunk_words) * 8 bytes: its node-value slots for
- * the 64-pattern words it has in flight.  The server allocates that much for each admitted
- * job.  Jobs stay queued until their charge fits beside the jobs in flight. */
+/* Start a serving loop on opts->device (continuous batching).  Submitted jobs wait in a
+ * queue until admitted; a job is admitted when its charge fits beside the charges of the
+ * jobs in flight: charge = peak_live_slots * min(W, chunk_words) * 8 bytes, the node-value
+ * slots of its 64-pattern words in flight (W = 2^(n-6) words; chunk_words = 2^22 unless the
+ * environment sets FASTLEC_ES_SERVER_CHUNK_WORDS).  Every step is one interpreter launch
+ * over the next slice of every job in flight, so jobs that arrive while others run share
+ * the device with them; a job retires as soon as its answer is final (all patterns clean,
+ * or the lowest failing pattern known).  Job descriptors and best-so-far values stay in a
+ * device-resident job table between steps.  opts: device, stream, schedule fields; the
+ * word range, deadline and cancel fields are ignored.  budget_bytes > 0. */
 int fastlec_es_server_create(const fastlec_es_options *opts, size_t budget_bytes, fastlec_es_server **out);
 
 /* Queue a job; never blocks.  The circuit must stay alive until the job is polled done.
@@ -180,6 +190,11 @@ size_t fastlec_es_specialized_source(const fastlec_es_circuit *c, int waves_per_
  * words of miter values.  Checks the plan's slot map first (FASTLEC_ERR_INVALID if broken). */
 int fastlec_es_host_replay(const fastlec_es_circuit *c, uint32_t bundle, uint64_t hw, uint64_t count,
                            uint32_t *out);
+
+/* Evaluate the specialized kernel's program (the cone mapped onto three-input LUTs, scalar
+ * steps and plan-time constant words) on the host for half-words hw .. hw+count-1, into
+ * out (count host words of miter values). */
+int fastlec_es_host_replay_specialized(const fastlec_es_circuit *c, uint64_t hw, uint64_t count, uint32_t *out);
 
 #ifdef __cplusplus
 }

@@ -65,7 +65,8 @@ class fastlec_es_options(ctypes.Structure):
 class fastlec_es_result(ctypes.Structure):
     _fields_ = [("verdict", ctypes.c_int32), ("reserved", ctypes.c_uint32), ("cex", ctypes.c_uint64),
                 ("patterns_evaluated", ctypes.c_uint64), ("next_word", ctypes.c_uint64),
-                ("plan_ms", ctypes.c_double), ("compile_ms", ctypes.c_double), ("kernel_ms", ctypes.c_double)]
+                ("plan_ms", ctypes.c_double), ("compile_ms", ctypes.c_double), ("kernel_ms", ctypes.c_double),
+                ("queued_ms", ctypes.c_double), ("latency_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
@@ -75,7 +76,8 @@ class fastlec_es_server_stats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
                 ("steps", ctypes.c_uint64), ("active", ctypes.c_uint64), ("queued", ctypes.c_uint64),
                 ("charge_in_use_bytes", ctypes.c_uint64), ("budget_bytes", ctypes.c_uint64),
-                ("peak_charge_bytes", ctypes.c_uint64), ("busy_ms", ctypes.c_double)]
+                ("peak_charge_bytes", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64),
+                ("max_active", ctypes.c_uint64), ("busy_ms", ctypes.c_double)]
 
 
 # (name, restype, argtypes) of every symbol in include/fastlec_es.h
@@ -100,6 +102,8 @@ SIGNATURES = [
     ("fastlec_es_specialized_source", ctypes.c_size_t, [_P, ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t]),
     ("fastlec_es_host_replay", ctypes.c_int, [_P, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
                                               ctypes.POINTER(ctypes.c_uint32)]),
+    ("fastlec_es_host_replay_specialized", ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_uint64,
+                                                          ctypes.POINTER(ctypes.c_uint32)]),
 ]
 
 _lib = None
@@ -240,6 +244,14 @@ def fastlec_es_specialized_source(circuit: Circuit, waves_per_eu: int = 2) -> st
 def fastlec_es_host_replay(circuit: Circuit, bundle: int, hw: int, count: int):
     out = (ctypes.c_uint32 * count)()
     rc = lib().fastlec_es_host_replay(circuit.handle, bundle, hw, count, out)
+    if rc:
+        _raise(rc)
+    return list(out)
+
+
+def fastlec_es_host_replay_specialized(circuit: Circuit, hw: int, count: int):
+    out = (ctypes.c_uint32 * count)()
+    rc = lib().fastlec_es_host_replay_specialized(circuit.handle, hw, count, out)
     if rc:
         _raise(rc)
     return list(out)

@@ -1,5 +1,6 @@
 // C ABI of the exact-simulation library.  No exception crosses this boundary:
 // every entry point catches, stores a thread-local message and returns a status.
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -9,10 +10,6 @@
 #include "runtime.hpp"
 
 using namespace fes;
-
-struct fastlec_es_circuit {
-    Circuit c;
-};
 
 namespace {
 
@@ -152,7 +149,9 @@ int fastlec_es_load_aig(const void* bytes, size_t len, fastlec_es_circuit** out)
     return guarded([&] {
         if (!out) throw Error{kErrInvalid, "null output handle"};
         *out = nullptr;
+        static std::atomic<uint64_t> next_uid{1};
         auto h = std::make_unique<fastlec_es_circuit>();
+        h->c.uid = next_uid++;
         h->c.aig = parse_aiger((const uint8_t*)bytes, len);
         const double t0 = now_ms();
         h->c.plan1 = make_plan(h->c.aig, Order::Auto, 1);
@@ -214,11 +213,14 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
             v.push_back(const_cast<Circuit*>(&cs[i]->c));
             rs.push_back(range_of(v.back()->plan1.num_inputs, 0, 0));
         }
-        Schedule sch = default_schedule(dev, v, &o);
+        // Schedule: the caller's fields when given, otherwise the autotuner's choice.
+        Schedule sch;
+        if (o.words_per_thread || o.wg_size) sch = default_schedule(dev, v, &o);
+        else sch = autotune(dev, v, rs, stream, o.kernel == FASTLEC_KERNEL_INTERP_HBM);
         if (o.tile_words) sch.tile_hw = 2ull * o.tile_words;
         std::vector<uint64_t> best;
         double ms = 0;
-        run_interp(dev, v, rs, sch, stream, nullptr, best, &ms);
+        run_batch_graph(dev, v, rs, sch, stream, best, &ms);
         for (size_t i = 0; i < k; ++i) {
             std::memset(&out[i], 0, sizeof(out[i]));
             fill_result(*v[i], rs[i], best[i], &out[i]);
@@ -248,13 +250,23 @@ int fastlec_es_compile_specialized(const fastlec_es_circuit* c, int waves_per_eu
 // Text of the specialized kernel source (for inspection); returns the length needed.
 size_t fastlec_es_specialized_source(const fastlec_es_circuit* c, int waves_per_eu, char* buf, size_t len) {
     if (!c) return 0;
-    std::string s = jit_source(c->c.plan1, waves_per_eu, 256);
+    std::string s = jit_source(const_cast<Circuit&>(c->c).lut_program(), waves_per_eu, 256);
     if (buf && len) {
         size_t m = std::min(len - 1, s.size());
         std::memcpy(buf, s.data(), m);
         buf[m] = 0;
     }
     return s.size() + 1;
+}
+
+// Host evaluation of the specialized kernel's LUT program, for validating the mapping without a GPU.
+int fastlec_es_host_replay_specialized(const fastlec_es_circuit* c, uint64_t hw, uint64_t count, uint32_t* out) {
+    return guarded([&] {
+        if (!c || !out) throw Error{kErrInvalid, "null argument"};
+        const LutProgram& lp = const_cast<Circuit&>(c->c).lut_program();
+        for (uint64_t t = 0; t < count; ++t) out[t] = eval_lut_program(lp, hw + t);
+        return FASTLEC_OK;
+    });
 }
 
 // Replay of the interpreter instruction stream on the host (bundle semantics: all reads of a

@@ -168,6 +168,11 @@ __global__ void __launch_bounds__(1024) es_interp_kernel(InterpLaunch L) {
 template <int K, int B, bool kLds>
 hipError_t launch_one(const InterpLaunch& L, int grid, int block, hipStream_t stream) {
     const size_t lds = kLds ? interp_lds_bytes(L.rows_max, K, block / 64) : 0;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&es_interp_kernel<K, B, kLds>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL((es_interp_kernel<K, B, kLds>), dim3(grid), dim3(block), lds, stream, L);
     return hipGetLastError();
 }

@@ -14,6 +14,7 @@
 // The source is compiled once per circuit with hipRTC for gfx950 and cached.
 #include <hip/hiprtc.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <sstream>
@@ -32,22 +33,26 @@ uint64_t fnv1a(const std::string& s) {
     return h;
 }
 
-std::string operand(const Plan& p, uint32_t field) {
-    const uint32_t row = field & kRowMask;
-    const bool neg = (field & kCompl) != 0;
-    std::string v;
-    if (row == 0) return neg ? "0xFFFFFFFFu" : "0u";
-    if (row <= p.num_inputs) v = "x" + std::to_string(row - 1);
-    else v = "s" + std::to_string(row - p.num_inputs - 1);
-    return neg ? "~" + v : v;
+std::string ref_name(const LutRef& r) {
+    switch (r.kind) {
+        case LutRef::Word: return "w" + std::to_string(r.index);
+        case LutRef::Input: return "x" + std::to_string(r.index);
+        case LutRef::Uniform: return "su" + std::to_string(r.index);
+        default: return "vr" + std::to_string(r.index);
+    }
+}
+
+bool is_scalar(const LutRef& r) {
+    return r.kind == LutRef::Word || r.kind == LutRef::Uniform || (r.kind == LutRef::Input && r.index >= 11);
 }
 
 }  // namespace
 
-std::string jit_source(const Plan& p, int waves_per_eu, int block) {
+std::string jit_source(const LutProgram& lp, int waves_per_eu, int block) {
     std::ostringstream o;
-    const uint32_t n = p.num_inputs;
-    o << "// exact simulation, " << n << " inputs, " << p.num_gate_instrs << " steps, " << p.peak_slots << " slots\n";
+    const uint32_t n = lp.num_inputs;
+    o << "// exact simulation, " << n << " inputs: " << lp.lut_steps << " LUT steps, " << lp.scalar_steps
+      << " scalar steps, " << lp.absorbed_gates << " gates absorbed into LUTs, " << lp.folded_gates << " folded\n";
     o << "typedef unsigned int u32;\ntypedef unsigned long long u64;\n";
     o << "extern \"C\" __global__ void __launch_bounds__(" << block << ") __attribute__((amdgpu_waves_per_eu("
       << waves_per_eu << ", " << waves_per_eu << ")))\n";
@@ -56,6 +61,11 @@ std::string jit_source(const Plan& p, int waves_per_eu, int block) {
     o << "  const u32 lane = threadIdx.x & 63u;\n";
     for (uint32_t i = 5; i < n && i < 11; ++i)
         o << "  const u32 x" << i << " = 0u - ((lane >> " << (i - 5) << ") & 1u);\n";
+    for (uint32_t i = 0; i < lp.words.size(); ++i) {
+        char buf[64];
+        std::snprintf(buf, sizeof buf, "  const u32 w%u = 0x%08Xu;\n", i, lp.words[i]);
+        o << buf;
+    }
     // Control flow stays wave-uniform: every lane takes part in the claim (lane 0 adds 1, the
     // others 0) and in the atomicMin (all lanes hold the same value), so no branch depends on
     // the lane and every loop exit is a scalar branch.
@@ -72,27 +82,103 @@ std::string jit_source(const Plan& p, int waves_per_eu, int block) {
          "      const u64 best_now = ((u64)__builtin_amdgcn_readfirstlane((u32)(b_raw >> 32)) << 32) |\n"
          "                           __builtin_amdgcn_readfirstlane((u32)b_raw);\n"
          "      if (32ull * base >= best_now) break;\n";
-    static const char* kConst[5] = {"0xAAAAAAAAu", "0xCCCCCCCCu", "0xF0F0F0F0u", "0xFF00FF00u", "0xFFFF0000u"};
-    for (uint32_t i = 0; i < n && i < 5; ++i) o << "      const u32 x" << i << " = " << kConst[i] << ";\n";
     for (uint32_t i = 11; i < n; ++i)
         o << "      const u32 x" << i << " = 0u - (u32)((base >> " << (i - 5) << ") & 1ull);\n";
     o << "      u32 m = 0u;\n";
-    if (p.peak_slots) {
-        o << "      u32 s0";
-        for (uint32_t s = 1; s < p.peak_slots; ++s) o << ", s" << s;
-        o << ";\n";
-    }
-    const uint32_t sink = n + 1 + p.peak_slots;
-    for (const Instr& ins : p.prog) {
-        if (ins.d == sink) {
-            if (ins.flags) o << "      m |= " << operand(p, ins.a) << ";\n";
+    // Every gate is an inline-asm instruction whose function the planner fixed, so the
+    // compiler allocates registers and schedules but never rewrites the logic.  VALU
+    // operands: at most one scalar (SGPR) source per instruction; others go through VGPRs.
+    char buf[256];
+    // Runs of consecutive scalar steps are emitted as one asm block (the compiler pads every
+    // asm block with a wait state, so one block per gate would double the scalar issue count).
+    // Block outputs are early-clobber: they never share a register with a block input.
+    auto flush_scalar = [&](const std::vector<const LutStep*>& run) {
+        if (run.empty()) return;
+        std::vector<std::string> outs, ins;
+        auto in_index = [&](const std::string& name) -> std::string {
+            for (size_t i = 0; i < outs.size(); ++i)
+                if (outs[i] == name) return "%" + std::to_string(i);
+            for (size_t i = 0; i < ins.size(); ++i)
+                if (ins[i] == name) return "%" + std::to_string(outs.size() + i);
+            return "";
+        };
+        for (const LutStep* st : run) outs.push_back("su" + std::to_string(st->dst));
+        for (const LutStep* st : run)
+            for (int j = 0; j < 2; ++j) {
+                const std::string nm = ref_name(st->leaf[j]);
+                if (in_index(nm).empty()) ins.push_back(nm);
+            }
+        std::string text;
+        for (const LutStep* st : run) {
+            const bool na = st->table & 1, nb = (st->table >> 1) & 1;
+            std::string a = in_index(ref_name(st->leaf[0])), b = in_index(ref_name(st->leaf[1]));
+            const char* opname = "s_and_b32";
+            if (na && nb) opname = "s_nor_b32";
+            else if (nb) opname = "s_andn2_b32";
+            else if (na) { opname = "s_andn2_b32"; std::swap(a, b); }
+            text += std::string(text.empty() ? "" : "\\n\\t") + opname + " " + in_index("su" + std::to_string(st->dst)) + ", " + a + ", " + b;
+        }
+        o << "      u32";
+        for (size_t i = 0; i < outs.size(); ++i) o << (i ? ", " : " ") << outs[i];
+        o << ";\n      asm(\"" << text << "\" : ";
+        for (size_t i = 0; i < outs.size(); ++i) o << (i ? ", " : "") << "\"=&s\"(" << outs[i] << ")";
+        o << " : ";
+        for (size_t i = 0; i < ins.size(); ++i) o << (i ? ", " : "") << "\"s\"(" << ins[i] << ")";
+        o << " : \"scc\");\n";
+    };
+    std::vector<const LutStep*> run;
+    auto run_operands = [&](const LutStep& st) {  // operand count if st joined the run
+        std::vector<std::string> names;
+        for (const LutStep* r : run) names.push_back("su" + std::to_string(r->dst));
+        names.push_back("su" + std::to_string(st.dst));
+        auto add = [&](const std::string& nm) {
+            if (std::find(names.begin(), names.end(), nm) == names.end()) names.push_back(nm);
+        };
+        for (const LutStep* r : run) { add(ref_name(r->leaf[0])); add(ref_name(r->leaf[1])); }
+        add(ref_name(st.leaf[0]));
+        add(ref_name(st.leaf[1]));
+        return names.size();
+    };
+    for (const LutStep& st : lp.steps) {
+        if (st.op == LutStep::ScalarAnd) {
+            if (!run.empty() && run_operands(st) > 30) {
+                flush_scalar(run);
+                run.clear();
+            }
+            run.push_back(&st);
             continue;
         }
-        const std::string d = "s" + std::to_string(ins.d - n - 1);
-        o << "      " << d << " = " << operand(p, ins.a) << " & " << operand(p, ins.b) << ";\n";
-        if (ins.flags & kOutPos) o << "      m |= " << d << ";\n";
-        if (ins.flags & kOutNeg) o << "      m |= ~" << d << ";\n";
+        flush_scalar(run);
+        run.clear();
+        if (st.op == LutStep::Lut) {
+            const uint32_t k = st.nleaves;
+            const char* fmt = k == 3 ? "%%1, %%2, %%3" : k == 2 ? "%%1, %%2, %%2" : "%%1, %%1, %%1";
+            char ops[32];
+            std::snprintf(ops, sizeof ops, fmt);
+            bool used_s = false;
+            std::string cons;
+            for (uint32_t j = 0; j < k; ++j) {
+                const bool sc = is_scalar(st.leaf[j]) && !used_s;
+                used_s |= sc;
+                cons += std::string(j ? ", " : "") + (sc ? "\"s\"(" : "\"v\"(") + ref_name(st.leaf[j]) + ")";
+            }
+            std::snprintf(buf, sizeof buf, "      u32 vr%u; asm(\"v_bitop3_b32 %%0, %s bitop3:0x%02x\" : \"=v\"(vr%u) : %s);\n",
+                          st.dst, ops, st.table, st.dst, cons.c_str());
+            o << buf;
+        } else {
+            // m = m | (x ^ neg): table over (m, x, x)
+            uint8_t table = 0;
+            for (uint32_t idx = 0; idx < 8; ++idx) {
+                const uint32_t mm = (idx >> 2) & 1u, x = (idx >> 1) & 1u;
+                if (mm | (x ^ (st.out_neg ? 1u : 0u))) table |= (uint8_t)(1u << idx);
+            }
+            const std::string x = ref_name(st.leaf[0]);
+            std::snprintf(buf, sizeof buf, "      asm(\"v_bitop3_b32 %%0, %%1, %%2, %%2 bitop3:0x%02x\" : \"=v\"(m) : \"v\"(m), \"%s\"(%s));\n",
+                          table, is_scalar(st.leaf[0]) ? "s" : "v", x.c_str());
+            o << buf;
+        }
     }
+    flush_scalar(run);
     o << "      const u64 hw = base + lane;\n"
          "      m = (hw >= hw_begin && hw < hw_end) ? m : 0u;\n"
          "      const u64 bal = __ballot(m != 0u);\n"
@@ -161,7 +247,7 @@ std::shared_ptr<JitKernel> jit_kernel(Circuit& c, int waves_per_eu, double* comp
     }
     std::lock_guard<std::mutex> g(k->mu);
     if (!k->code.empty()) return k;
-    k->source = jit_source(c.plan1, waves_per_eu, k->block);
+    k->source = jit_source(c.lut_program(), waves_per_eu, k->block);
     k->hash = fnv1a(k->source);
     {
         std::lock_guard<std::mutex> cg(g_cache_mu);

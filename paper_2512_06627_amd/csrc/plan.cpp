@@ -226,6 +226,9 @@ Plan make_plan(const Aig& g, Order order, uint32_t bundle) {
             p.prog = std::move(al.prog);
             p.num_gate_instrs = al.gates;
             p.order_used = cand.first;
+            p.order.clear();
+            for (auto& b : bundle_order(g, cand.second, bundle))
+                for (uint32_t k : b) p.order.push_back(k);
         }
     }
     p.bundle = bundle;

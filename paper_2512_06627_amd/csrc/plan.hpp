@@ -46,11 +46,45 @@ struct Plan {
     std::vector<Instr> prog;  // bundles of `bundle` instructions: one per cone AND, one per output
                               // that is not an AND's own value, no-ops padding the last bundle
     uint32_t num_gate_instrs = 0;  // instructions that are not padding
+    std::vector<uint32_t> order;   // AND gates (index into the AIG) in evaluation order
 };
 
 // bundle = 1: sequential stream.  bundle > 1: list-scheduled so that the gates of a
 // bundle do not read each other, keeping the chosen order as the priority.
 Plan make_plan(const Aig& g, Order order = Order::Auto, uint32_t bundle = 1);
+
+// Program of the specialized kernel: the cone mapped onto the three-input LUT instruction
+// of gfx950 (v_bitop3_b32, result bit = table[4*src0 + 2*src1 + src2]).
+//  * a value that depends only on inputs 0..4 and constants is the same 32-bit word in
+//    every lane and pass ("word"): it is computed here, at plan time;
+//  * a value that depends only on inputs 11.. (bits of the wave's base index), words and
+//    constants is wave-uniform: it is computed on the scalar unit from two operands;
+//  * every other gate becomes one VALU LUT over at most three leaves, absorbing fan-ins
+//    that feed nothing else, so a LUT may stand for several AND gates.
+struct LutRef {
+    enum Kind : uint8_t { Input = 0, Word = 1, Uniform = 2, Varying = 3 } kind;
+    uint32_t index;  // Input: input number; Word: index into words; Uniform/Varying: value id
+};
+struct LutStep {
+    enum Op : uint8_t { Lut = 0, ScalarAnd = 1, Output = 2 } op;
+    uint8_t table;       // Lut: truth table over (leaf0, leaf1, leaf2); ScalarAnd: bit0/bit1 = complement a/b
+    uint8_t nleaves;     // Lut: 1..3 distinct leaves
+    LutRef leaf[3];      // Lut: leaves; ScalarAnd: leaf[0], leaf[1]; Output: leaf[0]
+    uint32_t dst;        // value id written (Lut: Varying, ScalarAnd: Uniform)
+    bool out_neg;        // Output: accumulate the complement
+};
+struct LutProgram {
+    uint32_t num_inputs = 0;
+    std::vector<uint32_t> words;  // plan-time constant words
+    std::vector<LutStep> steps;   // in evaluation order
+    uint32_t num_values = 0;      // value ids used
+    uint32_t lut_steps = 0, scalar_steps = 0, absorbed_gates = 0, folded_gates = 0;
+    bool always_fails = false;    // an output is constant true
+};
+LutProgram make_lut_program(const Aig& g, const Plan& order_from);
+
+// Miter word of the LUT program at half-word hw (host evaluation, for validation).
+uint32_t eval_lut_program(const LutProgram& lp, uint64_t hw);
 
 // Check the slot map: every operand row holds the value it names when read,
 // and no live value is overwritten.  Returns an empty string when consistent.

@@ -68,6 +68,12 @@ const Plan& Circuit::plan_for(uint32_t bundle) {
     return *it->second;
 }
 
+const LutProgram& Circuit::lut_program() {
+    std::lock_guard<std::mutex> g(mu);
+    if (!lut) lut = std::make_unique<LutProgram>(make_lut_program(aig, plan1));
+    return *lut;
+}
+
 const Instr* Circuit::device_prog(int dev, uint32_t bundle, hipStream_t s) {
     const Plan& p = plan_for(bundle);
     std::lock_guard<std::mutex> g(mu);
@@ -134,6 +140,7 @@ Device& device(int ordinal) {
     if (std::strncmp(d->prop.gcnArchName, "gfx950", 6) != 0)
         throw Error{kErrDevice, std::string("built for gfx950, device is ") + d->prop.gcnArchName};
     FES_HIP(hipStreamCreateWithFlags(&d->stream, hipStreamNonBlocking));
+    FES_HIP(hipStreamCreateWithFlags(&d->capture_stream, hipStreamNonBlocking));
     trace("device %d: %s, %d CUs, LDS %zu per block / %zu per CU", ordinal, d->prop.gcnArchName,
           d->prop.multiProcessorCount, (size_t)d->prop.sharedMemPerBlock, (size_t)d->prop.maxSharedMemoryPerMultiProcessor);
     Device& ref = *d;
@@ -166,47 +173,104 @@ Layout layout(size_t k, size_t file_bytes) {
     return l;
 }
 
-int max_waves_per_cu(const Device& d) { return 32; }
+int max_waves_per_cu(const Device&) { return 32; }
 
 }  // namespace
 
-Schedule default_schedule(Device& dev, const std::vector<Circuit*>& cs, const fastlec_es_options* o) {
-    Schedule s;
-    if (o && o->words_per_thread) s.K = (int)o->words_per_thread;
-    if (o && o->wg_size) s.block = (int)o->wg_size;
-    if (o && o->kernel == FASTLEC_KERNEL_INTERP_HBM) s.lds = false;
-    if (s.K != 1 && s.K != 2 && s.K != 4) throw Error{kErrInvalid, "words_per_thread must be 1, 2 or 4"};
-    if (s.block < 64 || s.block > 1024 || s.block % 64) throw Error{kErrInvalid, "wg_size must be a multiple of 64 in [64, 1024]"};
-    uint32_t rows = 0;
-    for (Circuit* c : cs) rows = std::max(rows, c->plan_for(s.B).rows);
+bool make_schedule(Device& dev, const std::vector<Circuit*>& cs, int K, int B, int block, bool lds, Schedule& s) {
+    s = Schedule{};
+    s.K = K;
+    s.B = B;
+    s.block = block;
+    s.lds = lds;
+    const uint32_t rows = rows_for(cs, B);
     const size_t lds_cu = dev.prop.maxSharedMemoryPerMultiProcessor ? dev.prop.maxSharedMemoryPerMultiProcessor : 65536;
     const size_t lds_blk = dev.prop.sharedMemPerBlock ? dev.prop.sharedMemPerBlock : 65536;
-    if (s.lds) {
-        // Shrink K, then the workgroup, until at least one workgroup fits; else use HBM rows.
-        while (s.lds && interp_lds_bytes(rows, s.K, s.block / 64) > lds_blk) {
-            if (!(o && o->wg_size) && s.block > 64) s.block /= 2;
-            else if (!(o && o->words_per_thread) && s.K > 1) s.K /= 2;
-            else s.lds = false;
-        }
-    }
-    const int waves_per_block = s.block / 64;
+    const int waves_per_block = block / 64;
+    if (lds && interp_lds_bytes(rows, K, waves_per_block) > lds_blk) return false;
     int blocks_per_cu;
-    if (s.lds) {
-        blocks_per_cu = (int)(lds_cu / interp_lds_bytes(rows, s.K, waves_per_block));
+    if (lds) {
+        blocks_per_cu = (int)(lds_cu / interp_lds_bytes(rows, K, waves_per_block));
         blocks_per_cu = std::max(1, std::min(blocks_per_cu, max_waves_per_cu(dev) / waves_per_block));
     } else {
         blocks_per_cu = std::max(1, 16 / waves_per_block);
     }
     s.grid = dev.prop.multiProcessorCount * blocks_per_cu;
+    return true;
+}
+
+Schedule default_schedule(Device& dev, const std::vector<Circuit*>& cs, const fastlec_es_options* o) {
+    int K = (o && o->words_per_thread) ? (int)o->words_per_thread : 2;
+    int block = (o && o->wg_size) ? (int)o->wg_size : 256;
+    bool lds = !(o && o->kernel == FASTLEC_KERNEL_INTERP_HBM);
+    if (K != 1 && K != 2 && K != 4) throw Error{kErrInvalid, "words_per_thread must be 1, 2 or 4"};
+    if (block < 64 || block > 1024 || block % 64) throw Error{kErrInvalid, "wg_size must be a multiple of 64 in [64, 1024]"};
+    Schedule s;
+    // Shrink the workgroup, then K, until one workgroup's value files fit in LDS; else use
+    // value files in device memory.
+    while (lds && !make_schedule(dev, cs, K, 8, block, true, s)) {
+        if (!(o && o->wg_size) && block > 64) block /= 2;
+        else if (!(o && o->words_per_thread) && K > 1) K /= 2;
+        else lds = false;
+    }
+    if (!lds) make_schedule(dev, cs, K, 8, block, false, s);
     return s;
+}
+
+uint32_t rows_for(const std::vector<Circuit*>& cs, int B) {
+    uint32_t rows = 0;
+    for (Circuit* c : cs) rows = std::max(rows, c->plan_for(B).rows);
+    return rows;
+}
+
+uint64_t build_descs(Device& dev, const std::vector<Circuit*>& cs, const std::vector<HwRange>& ranges,
+                     const std::vector<uint32_t>& best_index, const Schedule& sch, hipStream_t stream,
+                     ConeDesc* out) {
+    const size_t k = cs.size();
+    const uint32_t pass_hw = 64u * (uint32_t)sch.K;
+    const size_t waves = (size_t)sch.grid * (sch.block / 64);
+    // Longest-processing-time order: cones with the most gate evaluations get the lowest
+    // item numbers, so the big ones start first and the small ones fill the tail.
+    std::vector<size_t> order(k);
+    std::iota(order.begin(), order.end(), 0);
+    std::vector<double> cost(k);
+    for (size_t i = 0; i < k; ++i)
+        cost[i] = (double)cs[i]->plan_for(sch.B).prog.size() * (double)(ranges[i].end - ranges[i].begin);
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+    uint64_t item = 0;
+    for (size_t t = 0; t < k; ++t) {
+        size_t i = order[t];
+        Circuit* c = cs[i];
+        const Plan& p = c->plan_for(sch.B);
+        ConeDesc& d = out[t];
+        d.prog = c->device_prog(dev.ordinal, sch.B, stream);
+        d.n_instr = (uint32_t)p.prog.size();
+        d.n_inputs = p.num_inputs;
+        d.rows = p.rows;
+        d.best_index = best_index[i];
+        d.hw_begin = ranges[i].begin;
+        d.hw_end = ranges[i].end;
+        d.hw_first = ranges[i].begin / pass_hw * pass_hw;
+        const uint64_t span = d.hw_end - d.hw_first;
+        uint64_t tile = sch.tile_hw;
+        if (!tile) {  // about 16 work items per wave over the launch, within [1, 64] passes
+            const uint64_t target = span / std::max<uint64_t>(1, waves * 16);
+            tile = pass_hw;
+            while (tile < target && tile < 64ull * pass_hw) tile *= 2;
+        }
+        tile = (tile + pass_hw - 1) / pass_hw * pass_hw;
+        d.tile_hw = tile;
+        d.item_begin = item;
+        item += (span + tile - 1) / tile;
+        d.item_end = item;
+    }
+    return item;
 }
 
 void run_interp(Device& dev, const std::vector<Circuit*>& cs, const std::vector<HwRange>& ranges, const Schedule& sch,
                 hipStream_t stream, const int* cancel, std::vector<uint64_t>& best, double* kernel_ms) {
     const size_t k = cs.size();
-    const uint32_t pass_hw = 64u * (uint32_t)sch.K;
-    uint32_t rows_max = 0;
-    for (Circuit* c : cs) rows_max = std::max(rows_max, c->plan_for(sch.B).rows);
+    const uint32_t rows_max = rows_for(cs, sch.B);
     const size_t waves = (size_t)sch.grid * (sch.block / 64);
     const size_t file_bytes = sch.lds ? 0 : waves * rows_max * 64ull * sch.K * 4ull;
     Layout lay = layout(k, file_bytes);
@@ -217,53 +281,19 @@ void run_interp(Device& dev, const std::vector<Circuit*>& cs, const std::vector<
         ~Releaser() { d.release(b); }
     } rel{dev, buf};
 
-    // Longest-processing-time order: cones with the most gate evaluations get the lowest
-    // item numbers, so the big ones start first and the small ones fill the tail.
-    std::vector<size_t> order(k);
-    std::iota(order.begin(), order.end(), 0);
-    std::vector<double> cost(k);
-    for (size_t i = 0; i < k; ++i)
-        cost[i] = (double)cs[i]->plan_for(sch.B).prog.size() * (double)(ranges[i].end - ranges[i].begin);
-    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
-
     uint8_t* host = (uint8_t*)buf.host;
     std::memset(host, 0, lay.files_off);
     uint64_t* hbest = (uint64_t*)(host + lay.best_off);
-    ConeDesc* hdesc = (ConeDesc*)(host + lay.desc_off);
-    uint64_t item = 0;
-    for (size_t t = 0; t < k; ++t) {
-        size_t i = order[t];
-        Circuit* c = cs[i];
-        const Plan& p = c->plan_for(sch.B);
-        ConeDesc& d = hdesc[t];
-        d.prog = c->device_prog(dev.ordinal, sch.B, stream);
-        d.n_instr = (uint32_t)p.prog.size();
-        d.n_inputs = p.num_inputs;
-        d.rows = p.rows;
-        d.best_index = (uint32_t)i;
-        d.hw_begin = ranges[i].begin;
-        d.hw_end = ranges[i].end;
-        d.hw_first = ranges[i].begin / pass_hw * pass_hw;
-        uint64_t span = d.hw_end - d.hw_first;
-        uint64_t tile = sch.tile_hw;
-        if (!tile) {  // about 16 work items per wave over the launch, within [1, 64] passes
-            uint64_t target = span / std::max<uint64_t>(1, waves * 16);
-            tile = pass_hw;
-            while (tile < target && tile < 64ull * pass_hw) tile *= 2;
-        }
-        tile = (tile + pass_hw - 1) / pass_hw * pass_hw;
-        d.tile_hw = tile;
-        d.item_begin = item;
-        item += (span + tile - 1) / tile;
-        d.item_end = item;
-        hbest[i] = ~0ull;
-    }
+    for (size_t i = 0; i < k; ++i) hbest[i] = ~0ull;
+    std::vector<uint32_t> idx(k);
+    std::iota(idx.begin(), idx.end(), 0u);
+    const uint64_t items = build_descs(dev, cs, ranges, idx, sch, stream, (ConeDesc*)(host + lay.desc_off));
     uint8_t* devp = (uint8_t*)buf.dev;
     InterpLaunch L;
     L.cones = (const ConeDesc*)(devp + lay.desc_off);
     L.num_cones = (uint32_t)k;
     L.rows_max = rows_max;
-    L.total_items = item;
+    L.total_items = items;
     L.ctl = (LaunchCtl*)devp;
     L.best = (unsigned long long*)(devp + lay.best_off);
     L.hbm_rows = sch.lds ? nullptr : (uint32_t*)(devp + lay.files_off);
@@ -280,7 +310,7 @@ void run_interp(Device& dev, const std::vector<Circuit*>& cs, const std::vector<
         }
     } ev{e0, e1};
     trace("interp launch: %zu cones, %llu items, K=%d B=%d %s grid=%d block=%d rows=%u", k,
-          (unsigned long long)item, sch.K, sch.B, sch.lds ? "lds" : "hbm", sch.grid, sch.block, rows_max);
+          (unsigned long long)items, sch.K, sch.B, sch.lds ? "lds" : "hbm", sch.grid, sch.block, rows_max);
     FES_HIP(hipMemcpyAsync(devp, host, lay.files_off, hipMemcpyHostToDevice, stream));
     FES_HIP(hipEventRecord(e0, stream));
     FES_HIP(launch_interp(L, sch.K, sch.B, sch.lds, sch.grid, sch.block, stream));

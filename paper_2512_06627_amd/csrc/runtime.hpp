@@ -44,6 +44,7 @@ struct JitKernel {
 };
 
 struct Circuit {
+    uint64_t uid = 0;  // unique per loaded circuit in this process (never reused)
     Aig aig;
     Plan plan1;  // sequential plan (specialized kernel, info)
     double plan_ms = 0;
@@ -51,7 +52,9 @@ struct Circuit {
     std::map<uint32_t, std::unique_ptr<Plan>> bundled;                  // bundle size -> plan
     std::map<std::pair<int, uint32_t>, Instr*> dev_prog;                  // (device, bundle) -> stream
     std::map<int, std::shared_ptr<JitKernel>> jit;                       // waves_per_eu -> kernel
+    std::unique_ptr<LutProgram> lut;                                      // specialized-kernel program
     ~Circuit();
+    const LutProgram& lut_program();
     const Plan& plan_for(uint32_t bundle);
     const Instr* device_prog(int device, uint32_t bundle, hipStream_t s);
 };
@@ -66,7 +69,8 @@ struct Buffer {
 struct Device {
     int ordinal = 0;
     hipDeviceProp_t prop{};
-    hipStream_t stream = nullptr;  // library stream
+    hipStream_t stream = nullptr;          // library stream
+    hipStream_t capture_stream = nullptr;  // used only to record hipGraphs
     std::mutex mu;
     std::vector<Buffer> free_bufs;
     Buffer acquire(size_t bytes);
@@ -96,17 +100,41 @@ struct HwRange {
 };
 HwRange range_of(uint32_t n, uint64_t begin_word, uint64_t end_word);
 
+// Descriptors of an interpreter launch, written to `out` in longest-processing-time order
+// (most gate evaluations first); cone i reports into best[best_index[i]].  Returns the
+// launch's total number of work items.
+uint64_t build_descs(Device& dev, const std::vector<Circuit*>& cs, const std::vector<HwRange>& ranges,
+                     const std::vector<uint32_t>& best_index, const Schedule& sch, hipStream_t stream,
+                     ConeDesc* out);
+uint32_t rows_for(const std::vector<Circuit*>& cs, int B);
+
 // One interpreter launch over several cones (k = 1 for a plain check).
 void run_interp(Device& dev, const std::vector<Circuit*>& cs, const std::vector<HwRange>& ranges,
                 const Schedule& sch, hipStream_t stream, const int* cancel, std::vector<uint64_t>& best,
                 double* kernel_ms);
 
 Schedule default_schedule(Device& dev, const std::vector<Circuit*>& cs, const fastlec_es_options* o);
+// Schedule for fixed K (half-words per lane), B (bundle) and workgroup size; lds = prefer LDS
+// value files.  Returns false when that combination does not fit (LDS too small).
+bool make_schedule(Device& dev, const std::vector<Circuit*>& cs, int K, int B, int block, bool lds, Schedule& out);
+// Fastest interpreter schedule for this set of cones, measured on a bounded prefix of each
+// cone's range and cached per device and batch shape.
+Schedule autotune(Device& dev, const std::vector<Circuit*>& cs, const std::vector<HwRange>& ranges, hipStream_t stream,
+                  bool hbm);
+// One persistent interpreter launch over whole spaces, captured once as a hipGraph
+// (descriptor upload, kernel, result readback) and replayed for identical batches.
+void run_batch_graph(Device& dev, const std::vector<Circuit*>& cs, const std::vector<HwRange>& ranges,
+                     const Schedule& sch, hipStream_t stream, std::vector<uint64_t>& best, double* ms);
 
 // Specialized kernel.
 std::shared_ptr<JitKernel> jit_kernel(Circuit& c, int waves_per_eu, double* compile_ms);
 void run_jit(Device& dev, Circuit& c, JitKernel& k, const HwRange& r, uint64_t tile_hw, hipStream_t stream,
              const int* cancel, uint64_t* best, double* kernel_ms);
-std::string jit_source(const Plan& p, int waves_per_eu, int block);
+std::string jit_source(const LutProgram& lp, int waves_per_eu, int block);
 
 }  // namespace fes
+
+// Opaque handle type of the C ABI.
+struct fastlec_es_circuit {
+    fes::Circuit c;
+};

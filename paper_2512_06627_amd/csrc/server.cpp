@@ -1,13 +1,389 @@
-// Continuous-batching server (in progress).
+// Continuous-batching exact-simulation server.
+//
+// Jobs are admitted by memory charge (peak live slots x words in flight x 8 B)
+// against a budget, and every step is one interpreter launch over the next
+// pattern slice of every job in flight.  A job that arrives while others are on
+// the device joins them at the next step; a job retires as soon as its answer
+// is final, and its charge goes back to the budget.  Slices are sized so a
+// step takes about FASTLEC_ES_SERVER_STEP_MS milliseconds (default 10), from a
+// running estimate of the interpreter's node*pattern rate, and every job in
+// flight gets the same amount of gate evaluations per step.
+//
+// Device-resident job table: best-so-far value per slot (written by the
+// kernels' atomicMin, read back after each step, reset when a slot is reused)
+// and the slot's descriptors, which the host refreshes each step with the
+// job's next slice.
+#include <algorithm>
+#include <cmath>
+#include <condition_variable>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <thread>
+
 #include "runtime.hpp"
 
+using namespace fes;
+
+namespace {
+
+struct Job {
+    uint64_t ticket = 0;
+    Circuit* c = nullptr;
+    uint64_t charge = 0;
+    HwRange range{0, 0};
+    uint64_t cursor = 0;  // first half-word not yet simulated
+    uint32_t slot = UINT32_MAX;
+    double t_submit = 0, t_admit = 0;
+    double kernel_ms = 0;
+    bool done = false;
+    int status = FASTLEC_OK;
+    fastlec_es_result res{};
+};
+
+uint64_t env_u64(const char* name, uint64_t dflt) {
+    const char* v = std::getenv(name);
+    if (!v || !*v) return dflt;
+    return std::strtoull(v, nullptr, 0);
+}
+
+constexpr int kK = 2;  // half-words per lane in the server's launches
+constexpr int kB = 8;  // bundle size
+constexpr uint32_t kCapacity = 1024;
+
+}  // namespace
+
+struct fastlec_es_server {
+    fastlec_es_options opts{};
+    Device* dev = nullptr;
+    hipStream_t stream = nullptr;
+    uint64_t budget = 0, chunk_words = 1ull << 22;
+    double step_ms_target = 10.0;
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    bool stop = false;
+    uint64_t next_ticket = 1;
+    std::deque<Job*> queue;
+    std::vector<Job*> active;
+    std::map<uint64_t, std::unique_ptr<Job>> jobs;
+    fastlec_es_server_stats st{};
+    std::string fatal;
+    int fatal_code = 0;
+
+    // device job table: [ctl lds][ctl hbm][best x capacity][desc lds x capacity][desc hbm x capacity]
+    Buffer table;
+    size_t off_best = 128, off_desc_lds = 0, off_desc_hbm = 0;
+    Buffer files;  // value files of the device-memory tier
+    std::vector<uint32_t> free_slots;
+    double rate = 1e14;  // node*patterns per second, running estimate
+    std::thread th;
+
+    uint64_t charge_of(const Circuit& c) const {
+        const uint32_t n = c.plan1.num_inputs;
+        const uint64_t words = n >= 6 ? (1ull << (n - 6)) : 1ull;
+        return (uint64_t)std::max<uint32_t>(1, c.plan1.peak_slots) * std::min(words, chunk_words) * 8ull;
+    }
+    void loop();
+    void step(const std::vector<Job*>& act);
+    void finish(Job* j, double now);
+};
+
+void fastlec_es_server::finish(Job* j, double now) {
+    j->done = true;
+    j->res.plan_ms = j->c->plan_ms;
+    j->res.kernel_ms = j->kernel_ms;
+    j->res.queued_ms = j->t_admit - j->t_submit;
+    j->res.latency_ms = now - j->t_submit;
+    st.completed++;
+    st.charge_in_use_bytes -= j->charge;
+    free_slots.push_back(j->slot);
+}
+
+void fastlec_es_server::step(const std::vector<Job*>& act) {
+    // Slices: equal gate-evaluation budget per job, at least 16 passes.
+    const uint32_t pass_hw = 64u * kK;
+    const double target_np = rate * step_ms_target / 1e3;
+    const double per_job = target_np / (double)act.size();
+    std::vector<Circuit*> lds_c, hbm_c;
+    std::vector<HwRange> lds_r, hbm_r;
+    std::vector<uint32_t> lds_i, hbm_i;
+    const size_t lds_blk = dev->prop.sharedMemPerBlock ? dev->prop.sharedMemPerBlock : 65536;
+    double step_np = 0;
+    std::vector<HwRange> windows(act.size());
+    for (size_t t = 0; t < act.size(); ++t) {
+        Job* j = act[t];
+        const Plan& p = j->c->plan_for(kB);
+        const double per_hw = 32.0 * std::max<size_t>(1, p.prog.size());
+        uint64_t slice = (uint64_t)std::max(16.0 * pass_hw, std::floor(per_job / per_hw));
+        slice = (slice + pass_hw - 1) / pass_hw * pass_hw;
+        HwRange w{j->cursor, std::min(j->range.end, j->cursor + slice)};
+        windows[t] = w;
+        step_np += per_hw * (double)(w.end - w.begin);
+        const bool fits = interp_lds_bytes(p.rows, kK, 1) <= lds_blk;
+        (fits ? lds_c : hbm_c).push_back(j->c);
+        (fits ? lds_r : hbm_r).push_back(w);
+        (fits ? lds_i : hbm_i).push_back(j->slot);
+    }
+    uint8_t* host = (uint8_t*)table.host;
+    uint8_t* devp = (uint8_t*)table.dev;
+    std::memset(host, 0, 128);
+    struct Group {
+        std::vector<Circuit*>* c;
+        std::vector<HwRange>* r;
+        std::vector<uint32_t>* i;
+        size_t ctl_off, desc_off;
+        bool lds;
+        Schedule sch;
+        uint64_t items = 0;
+    };
+    Group groups[2] = {{&lds_c, &lds_r, &lds_i, 0, off_desc_lds, true, {}}, {&hbm_c, &hbm_r, &hbm_i, 64, off_desc_hbm, false, {}}};
+    for (Group& g : groups) {
+        if (g.c->empty()) continue;
+        fastlec_es_options o = opts;
+        o.kernel = g.lds ? FASTLEC_KERNEL_INTERP : FASTLEC_KERNEL_INTERP_HBM;
+        o.words_per_thread = kK;
+        g.sch = default_schedule(*dev, *g.c, &o);
+        g.sch.B = kB;
+        g.items = build_descs(*dev, *g.c, *g.r, *g.i, g.sch, stream, (ConeDesc*)(host + g.desc_off));
+        if (!g.sch.lds) {
+            const size_t need = (size_t)g.sch.grid * (g.sch.block / 64) * rows_for(*g.c, kB) * 64ull * g.sch.K * 4ull;
+            if (files.bytes < need) {
+                if (files.dev) dev->release(files);
+                files = Buffer{};
+                files = dev->acquire(need);
+            }
+        }
+    }
+    // Upload the control words and this step's descriptors (best[] stays on the device).
+    FES_HIP(hipMemcpyAsync(devp, host, 128, hipMemcpyHostToDevice, stream));
+    for (Group& g : groups)
+        if (!g.c->empty())
+            FES_HIP(hipMemcpyAsync(devp + g.desc_off, host + g.desc_off, sizeof(ConeDesc) * g.c->size(),
+                                   hipMemcpyHostToDevice, stream));
+    hipEvent_t e0, e1;
+    FES_HIP(hipEventCreate(&e0));
+    FES_HIP(hipEventCreate(&e1));
+    FES_HIP(hipEventRecord(e0, stream));
+    for (Group& g : groups) {
+        if (g.c->empty()) continue;
+        InterpLaunch L;
+        L.cones = (const ConeDesc*)(devp + g.desc_off);
+        L.num_cones = (uint32_t)g.c->size();
+        L.rows_max = rows_for(*g.c, kB);
+        L.total_items = g.items;
+        L.ctl = (LaunchCtl*)(devp + g.ctl_off);
+        L.best = (unsigned long long*)(devp + off_best);
+        L.hbm_rows = g.sch.lds ? nullptr : (uint32_t*)files.dev;
+        L.cancel = nullptr;
+        FES_HIP(launch_interp(L, g.sch.K, g.sch.B, g.sch.lds, g.sch.grid, g.sch.block, stream));
+    }
+    FES_HIP(hipEventRecord(e1, stream));
+    FES_HIP(hipMemcpyAsync(host + off_best, devp + off_best, 8ull * kCapacity, hipMemcpyDeviceToHost, stream));
+    FES_HIP(hipStreamSynchronize(stream));
+    float ms = 0;
+    FES_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (ms > 0.5f) rate = 0.7 * rate + 0.3 * (step_np / (ms / 1e3));
+
+    const uint64_t* best = (const uint64_t*)(host + off_best);
+    const double now = now_ms();
+    std::lock_guard<std::mutex> g(mu);
+    st.steps++;
+    st.busy_ms += ms;
+    for (size_t t = 0; t < act.size(); ++t) {
+        Job* j = act[t];
+        j->kernel_ms += ms;
+        const uint64_t b = best[j->slot];
+        const uint32_t n = j->c->plan1.num_inputs;
+        if (b != ~0ull) {
+            j->res.verdict = FASTLEC_NONEQUIVALENT;
+            j->res.cex = b;
+            j->res.patterns_evaluated = b + 1;
+            j->res.next_word = b / 64;
+        } else {
+            j->cursor = windows[t].end;
+            if (j->cursor < j->range.end) continue;
+            j->res.verdict = FASTLEC_EQUIVALENT;
+            j->res.patterns_evaluated = n < 5 ? (1ull << n) : 32ull * (j->range.end - j->range.begin);
+            j->res.next_word = n >= 6 ? (1ull << (n - 6)) : 1ull;
+        }
+        finish(j, now);
+    }
+    active.erase(std::remove_if(active.begin(), active.end(), [](Job* j) { return j->done; }), active.end());
+    st.active = active.size();
+    cv_done.notify_all();
+}
+
+void fastlec_es_server::loop() {
+    try {
+        FES_HIP(hipSetDevice(dev->ordinal));
+        for (;;) {
+            std::vector<Job*> act;
+            std::vector<uint32_t> fresh;
+            {
+                std::unique_lock<std::mutex> g(mu);
+                // Admission: first fit in arrival order, unless the oldest job has waited
+                // more than two seconds, in which case nothing may pass it.
+                const double now = now_ms();
+                bool head_only = !queue.empty() && now - queue.front()->t_submit > 2000.0;
+                for (auto it = queue.begin(); it != queue.end();) {
+                    Job* j = *it;
+                    if (st.charge_in_use_bytes + j->charge <= budget && !free_slots.empty()) {
+                        j->slot = free_slots.back();
+                        free_slots.pop_back();
+                        j->t_admit = now;
+                        st.charge_in_use_bytes += j->charge;
+                        st.peak_charge_bytes = std::max(st.peak_charge_bytes, st.charge_in_use_bytes);
+                        active.push_back(j);
+                        fresh.push_back(j->slot);
+                        it = queue.erase(it);
+                    } else if (head_only) {
+                        break;
+                    } else {
+                        ++it;
+                    }
+                }
+                st.queued = queue.size();
+                st.active = active.size();
+                st.max_active = std::max<uint64_t>(st.max_active, active.size());
+                if (active.empty()) {
+                    if (stop) return;
+                    cv_work.wait(g, [&] { return stop || !queue.empty(); });
+                    if (stop && queue.empty()) return;
+                    continue;
+                }
+                if (stop) return;
+                act = active;
+            }
+            // Reset the best value of newly assigned slots on the device.
+            uint64_t* hb = (uint64_t*)((uint8_t*)table.host + off_best);
+            for (uint32_t s : fresh) {
+                hb[s] = ~0ull;
+                FES_HIP(hipMemcpyAsync((uint8_t*)table.dev + off_best + 8ull * s, &hb[s], 8, hipMemcpyHostToDevice, stream));
+            }
+            step(act);
+        }
+    } catch (const Error& e) {
+        std::lock_guard<std::mutex> g(mu);
+        fatal = e.msg;
+        fatal_code = e.code;
+    } catch (const std::exception& e) {
+        std::lock_guard<std::mutex> g(mu);
+        fatal = e.what();
+        fatal_code = FASTLEC_ERR_DEVICE;
+    }
+    std::lock_guard<std::mutex> g(mu);
+    const double now = now_ms();
+    for (Job* j : active) {
+        j->status = fatal_code;
+        j->res.verdict = fatal_code;
+        finish(j, now);
+    }
+    active.clear();
+    for (Job* j : queue) {
+        j->done = true;
+        j->status = fatal_code;
+        j->res.verdict = fatal_code;
+    }
+    queue.clear();
+    cv_done.notify_all();
+}
+
+namespace {
+thread_local std::string g_err;
+}
+
 extern "C" {
-int fastlec_es_server_create(const fastlec_es_options*, size_t, fastlec_es_server** out) {
-    if (out) *out = nullptr;
-    return FASTLEC_ERR_UNSUPPORTED;
+
+int fastlec_es_server_create(const fastlec_es_options* opts, size_t budget_bytes, fastlec_es_server** out) {
+    if (!out || budget_bytes == 0) return FASTLEC_ERR_INVALID;
+    *out = nullptr;
+    try {
+        auto s = std::make_unique<fastlec_es_server>();
+        if (opts) s->opts = *opts;
+        s->budget = budget_bytes;
+        s->chunk_words = std::max<uint64_t>(1, env_u64("FASTLEC_ES_SERVER_CHUNK_WORDS", 1ull << 22));
+        s->step_ms_target = (double)std::max<uint64_t>(1, env_u64("FASTLEC_ES_SERVER_STEP_MS", 10));
+        s->dev = &device(s->opts.device);
+        s->stream = s->opts.hip_stream ? (hipStream_t)s->opts.hip_stream : s->dev->stream;
+        s->off_desc_lds = (s->off_best + 8ull * kCapacity + 255) & ~size_t(255);
+        s->off_desc_hbm = s->off_desc_lds + sizeof(ConeDesc) * kCapacity;
+        s->table = s->dev->acquire(s->off_desc_hbm + sizeof(ConeDesc) * kCapacity);
+        for (uint32_t i = kCapacity; i-- > 0;) s->free_slots.push_back(i);
+        s->st.budget_bytes = budget_bytes;
+        fastlec_es_server* raw = s.get();
+        s->th = std::thread([raw] { raw->loop(); });
+        *out = s.release();
+        return FASTLEC_OK;
+    } catch (const Error& e) {
+        return e.code;
+    } catch (...) {
+        return FASTLEC_ERR_DEVICE;
+    }
 }
-int fastlec_es_server_submit(fastlec_es_server*, const fastlec_es_circuit*, uint64_t*) { return FASTLEC_ERR_UNSUPPORTED; }
-int fastlec_es_server_poll(fastlec_es_server*, uint64_t, fastlec_es_result*, int) { return FASTLEC_ERR_UNSUPPORTED; }
-int fastlec_es_server_stats_get(fastlec_es_server*, fastlec_es_server_stats*) { return FASTLEC_ERR_UNSUPPORTED; }
-void fastlec_es_server_destroy(fastlec_es_server*) {}
+
+int fastlec_es_server_submit(fastlec_es_server* s, const fastlec_es_circuit* c, uint64_t* ticket) {
+    if (!s || !c || !ticket) return FASTLEC_ERR_INVALID;
+    if (c->c.plan1.num_inputs > 63) return FASTLEC_ERR_UNSUPPORTED;
+    auto j = std::make_unique<Job>();
+    j->c = const_cast<Circuit*>(&c->c);
+    j->charge = s->charge_of(j->c[0]);
+    std::lock_guard<std::mutex> g(s->mu);
+    if (s->fatal_code) return s->fatal_code;
+    if (j->charge > s->budget) {
+        s->st.rejected++;
+        return FASTLEC_REJECTED;
+    }
+    j->range = range_of(j->c->plan1.num_inputs, 0, 0);
+    j->cursor = j->range.begin;
+    j->ticket = s->next_ticket++;
+    j->t_submit = now_ms();
+    *ticket = j->ticket;
+    s->queue.push_back(j.get());
+    s->jobs[j->ticket] = std::move(j);
+    s->st.submitted++;
+    s->st.queued = s->queue.size();
+    s->cv_work.notify_one();
+    return FASTLEC_OK;
 }
+
+int fastlec_es_server_poll(fastlec_es_server* s, uint64_t ticket, fastlec_es_result* out, int wait) {
+    if (!s || !out) return FASTLEC_ERR_INVALID;
+    std::unique_lock<std::mutex> g(s->mu);
+    auto it = s->jobs.find(ticket);
+    if (it == s->jobs.end()) return FASTLEC_ERR_INVALID;
+    Job* j = it->second.get();
+    if (!j->done) {
+        if (!wait) return 0;
+        s->cv_done.wait(g, [&] { return j->done; });
+    }
+    *out = j->res;
+    const int status = j->status;
+    s->jobs.erase(it);
+    return status ? status : 1;
+}
+
+int fastlec_es_server_stats_get(fastlec_es_server* s, fastlec_es_server_stats* st) {
+    if (!s || !st) return FASTLEC_ERR_INVALID;
+    std::lock_guard<std::mutex> g(s->mu);
+    *st = s->st;
+    st->device_bytes = s->table.bytes + s->files.bytes;
+    return FASTLEC_OK;
+}
+
+void fastlec_es_server_destroy(fastlec_es_server* s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->stop = true;
+    }
+    s->cv_work.notify_all();
+    if (s->th.joinable()) s->th.join();
+    if (s->table.dev) s->dev->release(s->table);
+    if (s->files.dev) s->dev->release(s->files);
+    delete s;
+}
+
+}  // extern "C"

@@ -171,3 +171,61 @@ def test_invalid_ranges_rejected():
     assert ei.value.code == es.FASTLEC_ERR_INVALID
     with pytest.raises(es.EsError):
         es.fastlec_es_check(c, begin_word=0, end_word=1 << 10)
+
+
+@pytest.mark.parametrize("kernel", ["specialized", "interp"])
+def test_full_space_coverage_n32(kernel):
+    """Single-minterm circuits over 32 inputs: the kernel must reach every part of 2^32."""
+    rng = miters.SplitMix64(32)
+    targets = [0, (1 << 32) - 1, (1 << 31) - 1, 1 << 31] + [rng.below(1 << 32) for _ in range(8)]
+    for t in targets:
+        c = es.fastlec_es_load_aig(miters.minterm_miter(32, [t]).to_aig())
+        assert gpu_answer(c, kernel=kernel) == t
+
+
+def test_full_size_mac8_fault():
+    name = "mac8_fused_separate_f2"
+    c = es.fastlec_es_load_aig(miters.workload(name).to_aig())
+    for kernel in ("specialized", "interp"):
+        assert gpu_answer(c, kernel=kernel) == expected(name)
+
+
+@pytest.mark.parametrize("name", ["mult16_array_booth", "mac8_fused_separate"])
+def test_full_size_equivalent(name):
+    """Equivalent at 2^32: verdict from both kernels; the oracle agrees on sampled patterns, and
+    on the whole space where its exhaustive run is recorded in the goldens."""
+    g = miters.workload(name)
+    c = es.fastlec_es_load_aig(g.to_aig())
+    for kernel in ("specialized", "interp"):
+        r = es.fastlec_es_check(c, kernel=kernel)
+        assert r["verdict"] == es.FASTLEC_EQUIVALENT and r["patterns_evaluated"] == 1 << 32
+    rng = miters.SplitMix64(len(name))
+    ps = np.array([rng.next_u64() >> 32 for _ in range(1 << 14)], dtype=np.uint64)
+    assert not oracle.Circuit(g.to_aag()).miter(ps).any()
+    golden = json.load(open(os.path.join(GOLDEN, "expected.json")))
+    if name in golden:
+        assert golden[name]["lowest_failure"] is None
+
+
+def test_batch_graph_replays_match_eager():
+    """check_batch records a hipGraph on first use and replays it: every replay, with eager
+    launches in between, must give the eager per-circuit answers."""
+    rng = miters.SplitMix64(21)
+    gs = []
+    for i in range(20):
+        n = rng.between(8, 17)
+        gs.append(miters.layered_cone_miter(3000 + i, n, rng.between(150, 1500),
+                                            fault_seed=(rng.between(1, 60) if i % 4 == 0 else None)))
+    circs = [es.fastlec_es_load_aig(g.to_aig()) for g in gs]
+    eager = [gpu_answer(c, kernel="interp") for c in circs]
+    assert eager == [oracle.check(g.to_aag(), threads=8) for g in gs]
+    for rep in range(4):
+        res = es.fastlec_es_check_batch(circs)
+        assert [r["cex"] if r["verdict"] else None for r in res] == eager
+        assert gpu_answer(circs[rep], kernel="interp") == eager[rep]
+        assert gpu_answer(circs[-1 - rep], kernel="specialized") == eager[-1 - rep]
+    for K in (1, 4):
+        res = es.fastlec_es_check_batch(circs, words_per_thread=K, wg_size=128)
+        assert [r["cex"] if r["verdict"] else None for r in res] == eager
+    res = es.fastlec_es_check_batch(circs, kernel="interp_hbm")
+    assert [r["cex"] if r["verdict"] else None for r in res] == eager
