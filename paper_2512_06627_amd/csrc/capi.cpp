@@ -85,7 +85,7 @@ void check_one(Circuit& c, const fastlec_es_options& o, fastlec_es_result* out) 
     const bool spec = use_specialized(c, o, full);
     std::shared_ptr<JitKernel> jk;
     double compile_ms = 0;
-    if (spec) jk = jit_kernel(c, 2, &compile_ms);
+    if (spec) jk = jit_kernel(c, specialized_waves_per_eu(), &compile_ms);
     Schedule sch;
     if (!spec) {
         std::vector<Circuit*> one{&c};

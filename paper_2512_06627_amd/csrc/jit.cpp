@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <sstream>
 
@@ -48,11 +49,23 @@ bool is_scalar(const LutRef& r) {
 
 }  // namespace
 
+int jit_passes(const LutProgram& lp) {
+    const char* v = std::getenv("FASTLEC_ES_JIT_PASSES");
+    const int want = (v && *v == '2') ? 2 : 1;
+    return lp.num_inputs >= 12 ? want : 1;
+}
+
 std::string jit_source(const LutProgram& lp, int waves_per_eu, int block) {
     std::ostringstream o;
     const uint32_t n = lp.num_inputs;
+    // P passes (64 half-words each) per loop iteration.  With P = 2 every wave-uniform value
+    // holds both passes in one 64-bit scalar register pair (pass 0 in the low half), so one
+    // scalar instruction serves two passes; the LUT steps are emitted once per pass.
+    const int P = jit_passes(lp);
+    const char* ut = P == 2 ? "u64" : "u32";
     o << "// exact simulation, " << n << " inputs: " << lp.lut_steps << " LUT steps, " << lp.scalar_steps
-      << " scalar steps, " << lp.absorbed_gates << " gates absorbed into LUTs, " << lp.folded_gates << " folded\n";
+      << " scalar steps, " << lp.absorbed_gates << " gates absorbed into LUTs, " << lp.folded_gates << " folded, "
+      << P << " passes per iteration\n";
     o << "typedef unsigned int u32;\ntypedef unsigned long long u64;\n";
     o << "extern \"C\" __global__ void __launch_bounds__(" << block << ") __attribute__((amdgpu_waves_per_eu("
       << waves_per_eu << ", " << waves_per_eu << ")))\n";
@@ -61,10 +74,14 @@ std::string jit_source(const LutProgram& lp, int waves_per_eu, int block) {
     o << "  const u32 lane = threadIdx.x & 63u;\n";
     for (uint32_t i = 5; i < n && i < 11; ++i)
         o << "  const u32 x" << i << " = 0u - ((lane >> " << (i - 5) << ") & 1u);\n";
+    char buf[320];
     for (uint32_t i = 0; i < lp.words.size(); ++i) {
-        char buf[64];
         std::snprintf(buf, sizeof buf, "  const u32 w%u = 0x%08Xu;\n", i, lp.words[i]);
         o << buf;
+        if (P == 2) {
+            std::snprintf(buf, sizeof buf, "  const u64 ww%u = 0x%08X%08Xull;\n", i, lp.words[i], lp.words[i]);
+            o << buf;
+        }
     }
     // Control flow stays wave-uniform: every lane takes part in the claim (lane 0 adds 1, the
     // others 0) and in the atomicMin (all lanes hold the same value), so no branch depends on
@@ -77,22 +94,56 @@ std::string jit_source(const LutProgram& lp, int waves_per_eu, int block) {
          "    if (cancel && __builtin_amdgcn_readfirstlane(__hip_atomic_load(cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))) break;\n"
          "    const u64 hw0 = hw_first + item * tile_hw;\n"
          "    const u64 hw_stop = hw0 + tile_hw < hw_end ? hw0 + tile_hw : hw_end;\n"
-         "    for (u64 base = hw0; base < hw_stop; base += 64) {\n"
+         "    for (u64 base = hw0; base < hw_stop; base += " << 64 * P << ") {\n"
          "      const u64 b_raw = __hip_atomic_load(best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);\n"
          "      const u64 best_now = ((u64)__builtin_amdgcn_readfirstlane((u32)(b_raw >> 32)) << 32) |\n"
          "                           __builtin_amdgcn_readfirstlane((u32)b_raw);\n"
          "      if (32ull * base >= best_now) break;\n";
-    for (uint32_t i = 11; i < n; ++i)
-        o << "      const u32 x" << i << " = 0u - (u32)((base >> " << (i - 5) << ") & 1ull);\n";
-    o << "      u32 m = 0u;\n";
+    std::string block_body;
+    if (P == 1 && specialized_emit_mode() == 1) {
+        // The compiler keeps its own values (claims, bounds, pointers, the ballot) in the
+        // registers that the block leaves alone: about 32 VGPRs and 30 SGPRs.
+        const int vgpr_budget = (waves_per_eu >= 4 ? 512 / waves_per_eu : 256) - 32;
+        BlockStats bs;
+        if (!emit_block_body(lp, vgpr_budget, 64, 0, 20, &block_body, &bs)) {
+            block_body.clear();
+            o << "      // one asm block would need " << bs.vgprs << " VGPRs and " << bs.sgprs << " SGPRs\n";
+        }
+        if (!block_body.empty())
+            o << "      // one asm block: " << bs.vgprs << " VGPRs, " << bs.sgprs << " SGPRs, " << bs.valu
+              << " VALU and " << bs.salu << " SALU instructions, " << bs.copies << " scalar-operand copies, " << bs.spills
+              << " values moved to VGPRs\n";
+    }
+    if (!block_body.empty()) {
+        o << "      const u32 base_lo = (u32)base, base_hi = (u32)(base >> 32);\n" << block_body;
+    } else {
+    for (uint32_t i = 11; i < n; ++i) {
+        if (P == 1)
+            o << "      const u32 x" << i << " = 0u - (u32)((base >> " << (i - 5) << ") & 1ull);\n";
+        else if (i == 11)  // bit 6 of the half-word index: clear in pass 0, set in pass 1 (base % 128 == 0)
+            o << "      const u64 x11 = 0xFFFFFFFF00000000ull;\n";
+        else
+            o << "      const u64 x" << i << " = 0ull - ((base >> " << (i - 5) << ") & 1ull);\n";
+    }
+    for (int q = 0; q < P; ++q) o << "      u32 m" << q << " = 0u;\n";
     // Every gate is an inline-asm instruction whose function the planner fixed, so the
     // compiler allocates registers and schedules but never rewrites the logic.  VALU
     // operands: at most one scalar (SGPR) source per instruction; others go through VGPRs.
-    char buf[256];
+    auto scalar_name = [&](const LutRef& r) {  // a scalar-step operand (full P-pass register)
+        if (r.kind == LutRef::Word) return std::string(P == 2 ? "ww" : "w") + std::to_string(r.index);
+        return ref_name(r);
+    };
+    auto pass_name = [&](const LutRef& r, int q) {  // a LUT operand for pass q
+        if (r.kind == LutRef::Varying) return "vr" + std::to_string(r.index) + "_" + std::to_string(q);
+        if (P == 2 && (r.kind == LutRef::Uniform || (r.kind == LutRef::Input && r.index >= 11)))
+            return "(u32)(" + ref_name(r) + (q ? " >> 32)" : ")");
+        return ref_name(r);
+    };
     // Runs of consecutive scalar steps are emitted as one asm block (the compiler pads every
     // asm block with a wait state, so one block per gate would double the scalar issue count).
     // Block outputs are early-clobber: they never share a register with a block input.
-    auto flush_scalar = [&](const std::vector<const LutStep*>& run) {
+    std::vector<const LutStep*> run;
+    auto flush_scalar = [&]() {
         if (run.empty()) return;
         std::vector<std::string> outs, ins;
         auto in_index = [&](const std::string& name) -> std::string {
@@ -105,28 +156,30 @@ std::string jit_source(const LutProgram& lp, int waves_per_eu, int block) {
         for (const LutStep* st : run) outs.push_back("su" + std::to_string(st->dst));
         for (const LutStep* st : run)
             for (int j = 0; j < 2; ++j) {
-                const std::string nm = ref_name(st->leaf[j]);
+                const std::string nm = scalar_name(st->leaf[j]);
                 if (in_index(nm).empty()) ins.push_back(nm);
             }
+        const char* sfx = P == 2 ? "_b64" : "_b32";
         std::string text;
         for (const LutStep* st : run) {
             const bool na = st->table & 1, nb = (st->table >> 1) & 1;
-            std::string a = in_index(ref_name(st->leaf[0])), b = in_index(ref_name(st->leaf[1]));
-            const char* opname = "s_and_b32";
-            if (na && nb) opname = "s_nor_b32";
-            else if (nb) opname = "s_andn2_b32";
-            else if (na) { opname = "s_andn2_b32"; std::swap(a, b); }
-            text += std::string(text.empty() ? "" : "\\n\\t") + opname + " " + in_index("su" + std::to_string(st->dst)) + ", " + a + ", " + b;
+            std::string a = in_index(scalar_name(st->leaf[0])), b = in_index(scalar_name(st->leaf[1]));
+            std::string opname = "s_and";
+            if (na && nb) opname = "s_nor";
+            else if (nb) opname = "s_andn2";
+            else if (na) { opname = "s_andn2"; std::swap(a, b); }
+            text += std::string(text.empty() ? "" : "\\n\\t") + opname + sfx + " " +
+                    in_index("su" + std::to_string(st->dst)) + ", " + a + ", " + b;
         }
-        o << "      u32";
+        o << "      " << ut;
         for (size_t i = 0; i < outs.size(); ++i) o << (i ? ", " : " ") << outs[i];
         o << ";\n      asm(\"" << text << "\" : ";
         for (size_t i = 0; i < outs.size(); ++i) o << (i ? ", " : "") << "\"=&s\"(" << outs[i] << ")";
         o << " : ";
         for (size_t i = 0; i < ins.size(); ++i) o << (i ? ", " : "") << "\"s\"(" << ins[i] << ")";
         o << " : \"scc\");\n";
+        run.clear();
     };
-    std::vector<const LutStep*> run;
     auto run_operands = [&](const LutStep& st) {  // operand count if st joined the run
         std::vector<std::string> names;
         for (const LutStep* r : run) names.push_back("su" + std::to_string(r->dst));
@@ -134,58 +187,62 @@ std::string jit_source(const LutProgram& lp, int waves_per_eu, int block) {
         auto add = [&](const std::string& nm) {
             if (std::find(names.begin(), names.end(), nm) == names.end()) names.push_back(nm);
         };
-        for (const LutStep* r : run) { add(ref_name(r->leaf[0])); add(ref_name(r->leaf[1])); }
-        add(ref_name(st.leaf[0]));
-        add(ref_name(st.leaf[1]));
+        for (const LutStep* r : run) { add(scalar_name(r->leaf[0])); add(scalar_name(r->leaf[1])); }
+        add(scalar_name(st.leaf[0]));
+        add(scalar_name(st.leaf[1]));
         return names.size();
     };
     for (const LutStep& st : lp.steps) {
         if (st.op == LutStep::ScalarAnd) {
-            if (!run.empty() && run_operands(st) > 30) {
-                flush_scalar(run);
-                run.clear();
-            }
+            if (!run.empty() && run_operands(st) > 30) flush_scalar();
             run.push_back(&st);
             continue;
         }
-        flush_scalar(run);
-        run.clear();
-        if (st.op == LutStep::Lut) {
-            const uint32_t k = st.nleaves;
-            const char* fmt = k == 3 ? "%%1, %%2, %%3" : k == 2 ? "%%1, %%2, %%2" : "%%1, %%1, %%1";
-            char ops[32];
-            std::snprintf(ops, sizeof ops, fmt);
-            bool used_s = false;
-            std::string cons;
-            for (uint32_t j = 0; j < k; ++j) {
-                const bool sc = is_scalar(st.leaf[j]) && !used_s;
-                used_s |= sc;
-                cons += std::string(j ? ", " : "") + (sc ? "\"s\"(" : "\"v\"(") + ref_name(st.leaf[j]) + ")";
+        flush_scalar();
+        for (int q = 0; q < P; ++q) {
+            if (st.op == LutStep::Lut) {
+                const uint32_t k = st.nleaves;
+                const char* ops = k == 3 ? "%1, %2, %3" : k == 2 ? "%1, %2, %2" : "%1, %1, %1";
+                bool used_s = false;
+                std::string cons;
+                for (uint32_t j = 0; j < k; ++j) {
+                    const bool sc = is_scalar(st.leaf[j]) && !used_s;
+                    used_s |= sc;
+                    cons += std::string(j ? ", " : "") + (sc ? "\"s\"(" : "\"v\"(") + pass_name(st.leaf[j], q) + ")";
+                }
+                std::snprintf(buf, sizeof buf, "      u32 vr%u_%d; asm(\"v_bitop3_b32 %%0, %s bitop3:0x%02x\" : \"=v\"(vr%u_%d) : %s);\n",
+                              st.dst, q, ops, st.table, st.dst, q, cons.c_str());
+                o << buf;
+            } else {
+                // m = m | (x ^ neg): table over (m, x, x)
+                uint8_t table = 0;
+                for (uint32_t idx = 0; idx < 8; ++idx) {
+                    const uint32_t mm = (idx >> 2) & 1u, x = (idx >> 1) & 1u;
+                    if (mm | (x ^ (st.out_neg ? 1u : 0u))) table |= (uint8_t)(1u << idx);
+                }
+                std::snprintf(buf, sizeof buf, "      asm(\"v_bitop3_b32 %%0, %%1, %%2, %%2 bitop3:0x%02x\" : \"=v\"(m%d) : \"v\"(m%d), \"%s\"(%s));\n",
+                              table, q, q, is_scalar(st.leaf[0]) ? "s" : "v", pass_name(st.leaf[0], q).c_str());
+                o << buf;
             }
-            std::snprintf(buf, sizeof buf, "      u32 vr%u; asm(\"v_bitop3_b32 %%0, %s bitop3:0x%02x\" : \"=v\"(vr%u) : %s);\n",
-                          st.dst, ops, st.table, st.dst, cons.c_str());
-            o << buf;
-        } else {
-            // m = m | (x ^ neg): table over (m, x, x)
-            uint8_t table = 0;
-            for (uint32_t idx = 0; idx < 8; ++idx) {
-                const uint32_t mm = (idx >> 2) & 1u, x = (idx >> 1) & 1u;
-                if (mm | (x ^ (st.out_neg ? 1u : 0u))) table |= (uint8_t)(1u << idx);
-            }
-            const std::string x = ref_name(st.leaf[0]);
-            std::snprintf(buf, sizeof buf, "      asm(\"v_bitop3_b32 %%0, %%1, %%2, %%2 bitop3:0x%02x\" : \"=v\"(m) : \"v\"(m), \"%s\"(%s));\n",
-                          table, is_scalar(st.leaf[0]) ? "s" : "v", x.c_str());
-            o << buf;
         }
     }
-    flush_scalar(run);
-    o << "      const u64 hw = base + lane;\n"
-         "      m = (hw >= hw_begin && hw < hw_end) ? m : 0u;\n"
-         "      const u64 bal = __ballot(m != 0u);\n"
-         "      if (bal) {\n"
-         "        const u32 l = (u32)__builtin_ctzll(bal);\n"
-         "        const u32 ml = __builtin_amdgcn_readlane(m, l);\n"
-         "        atomicMin(best, 32ull * (base + l) + (u32)__builtin_ctz(ml));\n"
+    flush_scalar();
+    }
+    // Lowest failing pattern of this iteration: passes in ascending order, then the lowest
+    // lane, then the lowest bit.
+    o << "      u64 p = ~0ull;\n";
+    for (int q = P - 1; q >= 0; --q) {
+        o << "      {\n"
+             "        const u64 hw = base + " << 64 * q << "u + lane;\n"
+             "        const u32 mq = (hw >= hw_begin && hw < hw_end) ? m" << q << " : 0u;\n"
+             "        const u64 bal = __ballot(mq != 0u);\n"
+             "        const u32 l = bal ? (u32)__builtin_ctzll(bal) : 0u;\n"
+             "        const u32 ml = __builtin_amdgcn_readlane(mq, l);\n"
+             "        if (bal) p = 32ull * (base + " << 64 * q << "u + l) + (u32)__builtin_ctz(ml);\n"
+             "      }\n";
+    }
+    o << "      if (p != ~0ull) {\n"
+         "        atomicMin(best, p);\n"
          "        break;\n"
          "      }\n"
          "    }\n"
@@ -233,6 +290,23 @@ std::map<uint64_t, std::vector<char>>& code_cache() {
 
 }  // namespace
 
+namespace {
+int env_int(const char* name, int dflt, int lo, int hi) {
+    const char* v = std::getenv(name);
+    if (!v || !*v) return dflt;
+    const int x = std::atoi(v);
+    return x < lo || x > hi ? dflt : x;
+}
+}  // namespace
+
+int specialized_emit_mode() { return env_int("FASTLEC_ES_JIT_EMIT", 0, 0, 1); }
+int specialized_waves_per_eu() { return env_int("FASTLEC_ES_JIT_WAVES", 2, 1, 8); }
+int specialized_scalar_policy() { return env_int("FASTLEC_ES_JIT_SCALAR", 0, 0, 2); }
+int specialized_block() {
+    const int b = env_int("FASTLEC_ES_JIT_BLOCK", 256, 64, 1024);
+    return b % 64 ? 256 : b;
+}
+
 std::shared_ptr<JitKernel> jit_kernel(Circuit& c, int waves_per_eu, double* compile_ms) {
     if (compile_ms) *compile_ms = 0;
     std::shared_ptr<JitKernel> k;
@@ -242,12 +316,13 @@ std::shared_ptr<JitKernel> jit_kernel(Circuit& c, int waves_per_eu, double* comp
         if (it != c.jit.end()) return it->second;
         k = std::make_shared<JitKernel>();
         k->waves_per_eu = waves_per_eu;
-        k->block = 256;
+        k->block = specialized_block();
         c.jit[waves_per_eu] = k;
     }
     std::lock_guard<std::mutex> g(k->mu);
     if (!k->code.empty()) return k;
     k->source = jit_source(c.lut_program(), waves_per_eu, k->block);
+    k->passes = jit_passes(c.lut_program());
     k->hash = fnv1a(k->source);
     {
         std::lock_guard<std::mutex> cg(g_cache_mu);
@@ -294,15 +369,16 @@ void run_jit(Device& dev, Circuit& c, JitKernel& k, const HwRange& r, uint64_t t
     }
     const int grid = dev.prop.multiProcessorCount * blocks_per_cu;
     const uint64_t waves = (uint64_t)grid * (k.block / 64);
-    uint64_t hw_first = r.begin / 64 * 64;
+    const uint64_t step = 64ull * (uint64_t)k.passes;  // half-words per loop iteration
+    uint64_t hw_first = r.begin / step * step;
     const uint64_t span = r.end - hw_first;
     uint64_t tile = tile_hw;
     if (!tile) {
         uint64_t target = span / std::max<uint64_t>(1, waves * 16);
-        tile = 64;
+        tile = step;
         while (tile < target && tile < 64ull * 64) tile *= 2;
     }
-    tile = (tile + 63) / 64 * 64;
+    tile = (tile + step - 1) / step * step;
     uint64_t total_items = (span + tile - 1) / tile;
 
     Buffer buf = dev.acquire(4096);

@@ -81,7 +81,9 @@ struct LutProgram {
     uint32_t lut_steps = 0, scalar_steps = 0, absorbed_gates = 0, folded_gates = 0;
     bool always_fails = false;    // an output is constant true
 };
-LutProgram make_lut_program(const Aig& g, const Plan& order_from);
+// scalar_policy: 0 = every wave-uniform gate on the scalar unit; 1 = only those without
+// plan-time-word operands; 2 = none (all gates in VALU LUTs).
+LutProgram make_lut_program(const Aig& g, const Plan& order_from, int scalar_policy = 0);
 
 // Miter word of the LUT program at half-word hw (host evaluation, for validation).
 uint32_t eval_lut_program(const LutProgram& lp, uint64_t hw);

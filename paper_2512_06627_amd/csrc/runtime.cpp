@@ -70,7 +70,7 @@ const Plan& Circuit::plan_for(uint32_t bundle) {
 
 const LutProgram& Circuit::lut_program() {
     std::lock_guard<std::mutex> g(mu);
-    if (!lut) lut = std::make_unique<LutProgram>(make_lut_program(aig, plan1));
+    if (!lut) lut = std::make_unique<LutProgram>(make_lut_program(aig, plan1, specialized_scalar_policy()));
     return *lut;
 }
 

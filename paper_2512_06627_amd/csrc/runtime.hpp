@@ -37,6 +37,7 @@ struct JitKernel {
     uint64_t hash = 0;
     int waves_per_eu = 2;
     int block = 256;
+    int passes = 1;  // 64-half-word passes per loop iteration; tiles are multiples of this
     double compile_ms = 0;
     std::mutex mu;
     std::map<int, std::pair<hipModule_t, hipFunction_t>> per_device;
@@ -126,11 +127,26 @@ Schedule autotune(Device& dev, const std::vector<Circuit*>& cs, const std::vecto
 void run_batch_graph(Device& dev, const std::vector<Circuit*>& cs, const std::vector<HwRange>& ranges,
                      const Schedule& sch, hipStream_t stream, std::vector<uint64_t>& best, double* ms);
 
-// Specialized kernel.
+// Specialized kernel.  Occupancy target (waves per SIMD) and workgroup size default to the
+// tuned values; FASTLEC_ES_JIT_WAVES and FASTLEC_ES_JIT_BLOCK override them.
+int specialized_waves_per_eu();
+int specialized_block();
+int specialized_scalar_policy();  // FASTLEC_ES_JIT_SCALAR: 0 all, 1 pure uniform only, 2 none
 std::shared_ptr<JitKernel> jit_kernel(Circuit& c, int waves_per_eu, double* compile_ms);
 void run_jit(Device& dev, Circuit& c, JitKernel& k, const HwRange& r, uint64_t tile_hw, hipStream_t stream,
              const int* cancel, uint64_t* best, double* kernel_ms);
 std::string jit_source(const LutProgram& lp, int waves_per_eu, int block);
+
+// The per-pass body as one asm statement with planner-assigned registers (v0.., s<sgpr_base>..).
+// Returns false, with the register counts in stats, when it needs more than the limits.
+struct BlockStats {
+    int vgprs = 0, sgprs = 0, word_operands = 0;
+    uint32_t valu = 0, salu = 0, copies = 0, spills = 0;
+};
+bool emit_block_body(const LutProgram& lp, int vgpr_limit, int sgpr_limit, int sgpr_base, int word_operand_limit,
+                     std::string* code, BlockStats* stats);
+int specialized_emit_mode();  // FASTLEC_ES_JIT_EMIT: 1 one asm block per pass, 0 one asm statement per gate
+int jit_passes(const LutProgram& lp);
 
 }  // namespace fes
 
