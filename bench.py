@@ -20,11 +20,30 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Integer-VALU roofline of MI355X: 256 CUs * 64 lanes * 2.4 GHz int32 lane-ops per second;
-# one lane-op evaluates one AND gate on 32 patterns.
-CUS, LANES, CLOCK_HZ = 256, 64, 2.4e9
-PEAK_LANE_OPS = CUS * LANES * CLOCK_HZ
-PEAK_NODE_PATTERNS = PEAK_LANE_OPS * 32
+# Integer-VALU roofline of MI355X.  The published fp32 vector rate, 157.3 TFLOP/s = 256 CUs x
+# 2.4 GHz x 128 lanes x 2 flops per FMA, gives 128 32-bit lanes per CU per cycle, and a 32-bit
+# bitwise op issues at that lane rate (two wave64 VALU instructions per CU per cycle).  One
+# lane-op evaluates one AND gate on 32 patterns.
+CUS, LANES_PER_CYCLE, CLOCK_HZ = 256, 128, 2.4e9
+PEAK_LANE_OPS = CUS * LANES_PER_CYCLE * CLOCK_HZ        # 7.86e13 int32 lane-ops/s
+PEAK_WAVE_INSTR = PEAK_LANE_OPS / 64                     # 1.23e12 wave64 VALU instructions/s
+PEAK_NODE_PATTERNS = PEAK_LANE_OPS * 32                   # 2.52e15 AND-node*patterns/s
+
+
+def executed_view(es, c, n, num_ands, kernel_s):
+    """Instructions the specialized kernel executes per 2,048-pattern pass (from its generated
+    body), and the VALU issue rate they imply."""
+    import re
+    src = es.fastlec_es_specialized_source(c, 2)
+    m = re.search(r"one asm block: (\d+) VGPRs, (\d+) SGPRs, (\d+) VALU and (\d+) SALU", src)
+    if not m:
+        return None
+    valu, salu = int(m.group(3)), int(m.group(4))
+    passes = 1 << max(0, n - 11)
+    rate = valu * passes / kernel_s
+    return {"valu_per_pass_body": valu, "salu_per_pass_body": salu, "passes": passes,
+            "valu_instr_per_s": rate, "valu_issue_peak": PEAK_WAVE_INSTR, "valu_issue_frac": rate / PEAK_WAVE_INSTR,
+            "and_gates_per_valu_instr": num_ands / valu}
 
 
 def cpu_baseline(aag: bytes, num_ands: int, target_s: float = 12.0):
@@ -48,9 +67,11 @@ def cpu_baseline(aag: bytes, num_ands: int, target_s: float = 12.0):
             "sample": f"patterns [0, {patterns}) of the same miter, {dt:.1f} s on {threads} threads"}
 
 
-def batch_leg(es, stream, seed: int = 4, count: int = 256, faulty: int = 26):
-    """256 XOR-dense layered cones (n ~ U{18..30}, ~U[200, 5000] AND gates, 26 faulty):
-    one persistent batched launch (autotuned, hipGraph) vs one plain check per cone."""
+def batch_leg(es, stream, seed: int = 4, count: int = 256, faulty: int = 26, n_range=(18, 30),
+              size_range=(200, 5000)):
+    """`count` XOR-dense layered cones (n ~ U{n_range}, ~U[size_range] AND gates, `faulty` of them
+    with an injected fault): one persistent batched launch (autotuned, hipGraph) vs one plain
+    check per cone, both on the interpreter kernel."""
     import miters
     rng = miters.SplitMix64(seed)
     bad = set()
@@ -59,7 +80,7 @@ def batch_leg(es, stream, seed: int = 4, count: int = 256, faulty: int = 26):
     t0 = time.perf_counter()
     cones, work = [], 0
     for i in range(count):
-        n, size = rng.between(18, 30), rng.between(200, 5000)
+        n, size = rng.between(*n_range), rng.between(*size_range)
         fault = rng.between(1, 1 << 20) if i in bad else None
         c = es.fastlec_es_load_aig(miters.layered_cone_miter(seed * 100000 + i, n, size, fault_seed=fault).to_aig())
         cones.append(c)
@@ -83,35 +104,42 @@ def batch_leg(es, stream, seed: int = 4, count: int = 256, faulty: int = 26):
         got = answers(es.fastlec_es_check_batch(cones, stream=stream))
         reps.append(time.perf_counter() - t0)
     t_batch = sorted(reps)[1]
-    return {"cones": count, "faulty_injected": faulty, "found_nonequivalent": sum(a is not None for a in got),
+    return {"cones": count, "n_range": list(n_range), "gates_range": list(size_range), "faulty_injected": faulty, "found_nonequivalent": sum(a is not None for a in got),
             "node_patterns_upper_bound": work, "plain_cones_per_s": count / t_plain,
             "batched_cones_per_s": count / t_batch, "batched_vs_plain_speedup": t_plain / t_batch,
             "identical_verdicts": plain == plain2 == first == got, "first_batch_call_s": t_first,
             "generate_s": gen_s}
 
 
-def serve_leg(es, stream, rate_hint: float, seed: int = 5, seconds: float = 30.0, max_requests: int = 400,
-              pool: int = 40, budget_gib: int = 64):
+def serve_leg(es, stream, seed: int = 5, seconds: float = 30.0, max_requests: int = 400,
+              pool: int = 40, budget_gib: int = 64, load: float = 0.7):
     """Poisson stream of cones (n ~ U{16..34}, ~U[500, 20000] AND gates, 10% faulty) served by
-    continuous batching with an HBM budget; arrival rate set to 0.7 of the capacity implied by
-    `rate_hint` (node*patterns/s).  Reports p50/p99 latency and checks every answer against the
-    same cone checked alone."""
+    continuous batching with an HBM budget.  Capacity is measured on the same server first (every
+    pool cone submitted at once; work = gates x patterns each job actually evaluated), and the
+    arrival rate is set to `load` of it.  Reports p50/p99 latency and checks every answer against
+    the same cone checked alone."""
     import miters
     rng = miters.SplitMix64(seed)
     t0 = time.perf_counter()
-    circs, works = [], []
+    circs, gates = [], []
     for i in range(pool):
         n, size = rng.between(16, 34), rng.between(500, 20000)
         fault = rng.between(1, 1 << 20) if rng.below(10) == 0 else None
         c = es.fastlec_es_load_aig(miters.layered_cone_miter(seed * 100000 + i, n, size, fault_seed=fault).to_aig())
-        info = c.info()
         circs.append(c)
-        works.append(info["num_instrs"] * (1 << info["num_pis"]))
+        gates.append(c.info()["num_ands_tfi"])
     gen_s = time.perf_counter() - t0
-    mean_service = (sum(works) / len(works)) / rate_hint
-    lam = 0.7 / mean_service
     srv = es.Server(budget_gib << 30, stream=None)
-    arrivals, tickets, which = [], [], []
+    t0 = time.perf_counter()
+    cal = [srv.poll(t, wait=True) for t in [srv.submit(c) for c in circs]]
+    cal_s = time.perf_counter() - t0
+    works = [g * r["patterns_evaluated"] for g, r in zip(gates, cal)]
+    capacity = sum(works) / cal_s
+    lam = load / (cal_s / pool)
+    print(json.dumps({"progress": "serve calibration", "seconds": cal_s, "capacity_node_patterns_per_s": capacity,
+                      "arrival_rate_per_s": lam}), file=sys.stderr, flush=True)
+    steps0 = srv.stats()["steps"]
+    tickets, which = [], []
     start = time.perf_counter()
     t_next = 0.0
     while len(tickets) < max_requests and t_next < seconds:
@@ -135,11 +163,12 @@ def serve_leg(es, stream, rate_hint: float, seed: int = 5, seconds: float = 30.0
     lat = sorted(r["latency_ms"] for r in results)
     q = lambda f: lat[min(len(lat) - 1, int(f * len(lat)))]
     done_work = sum(works[k] for k in which)
-    return {"requests": len(tickets), "arrival_rate_per_s": lam, "offered_load": 0.7, "wall_s": wall,
+    return {"requests": len(tickets), "arrival_rate_per_s": lam, "offered_load": load,
+            "capacity_node_patterns_per_s": capacity, "calibration_s": cal_s, "wall_s": wall,
             "latency_ms_p50": q(0.50), "latency_ms_p99": q(0.99), "requests_per_s": len(tickets) / wall,
             "node_patterns_per_s": done_work / wall, "max_jobs_in_flight": st["max_active"],
             "peak_charge_bytes": st["peak_charge_bytes"], "budget_bytes": st["budget_bytes"],
-            "server_device_bytes": st["device_bytes"], "steps": st["steps"],
+            "server_device_bytes": st["device_bytes"], "steps": st["steps"] - steps0,
             "each_equal_alone": served == [alone[k] for k in which], "pool": pool, "generate_s": gen_s}
 
 
@@ -222,8 +251,10 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_NODE_PATTERNS,
                      "unit": "node*patterns/s", "frac": achieved / PEAK_NODE_PATTERNS, "traffic": None,
                      "kernel_ms_median": k_ms,
-                     "note": "peak = 256 CU * 64 lanes * 2.4 GHz int32 lane-ops * 32 patterns per lane-op "
-                             "(one lane-op per AND gate); achieved = N*2^n / mean kernel time (HIP events)"},
+                     "note": "peak = 256 CU * 128 int32 lanes/cycle * 2.4 GHz * 32 patterns per lane-op "
+                             "(one lane-op per AND gate); achieved = N*2^n / mean kernel time (HIP events); "
+                             "a LUT instruction evaluates several AND gates, see executed"},
+        "executed": executed_view(es, c, n, N, sum(kernel_ms) / len(kernel_ms) / 1e3) if a.kernel == "specialized" else None,
         "load_ms": load_ms,
         "compile_ms": compile_ms,
         "all_steps_equivalent": bool(for_each_ok),
@@ -241,8 +272,10 @@ def main():
         print(json.dumps({"progress": "mac8", **sec["mac8"]}), file=sys.stderr, flush=True)
         sec["batch"] = batch_leg(es, stream)
         print(json.dumps({"progress": "batch", **sec["batch"]}), file=sys.stderr, flush=True)
-        interp_rate = sec["batch"]["node_patterns_upper_bound"] / (256 / sec["batch"]["batched_cones_per_s"])
-        sec["serve"] = serve_leg(es, stream, rate_hint=interp_rate, seconds=a.serve_seconds)
+        sec["batch_small"] = batch_leg(es, stream, seed=6, count=2048, faulty=205, n_range=(8, 16),
+                                       size_range=(50, 2000))
+        print(json.dumps({"progress": "batch_small", **sec["batch_small"]}), file=sys.stderr, flush=True)
+        sec["serve"] = serve_leg(es, stream, seconds=a.serve_seconds)
         out["secondary"] = sec
     print(json.dumps(out), flush=True)
 

@@ -1,5 +1,7 @@
 // Interpreter schedule autotuner and hipGraph-captured batch launches.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 
@@ -42,9 +44,16 @@ Schedule autotune(Device& dev, const std::vector<Circuit*>& cs, const std::vecto
         work += (double)cs[i]->plan1.num_gate_instrs * 32.0 * (double)(ranges[i].end - ranges[i].begin);
     TuneKey key{dev.ordinal, log2_bucket(rows_for(cs, 8)), log2_bucket((double)cs.size()), log2_bucket(work), hbm};
     {
+        // A cached choice is re-fitted to this batch: the key buckets the value-file rows, and
+        // within a bucket a larger cone may no longer fit the chosen workgroup in LDS.
         std::lock_guard<std::mutex> g(g_tune_mu);
         auto it = tune_cache().find(key);
-        if (it != tune_cache().end()) return it->second;
+        if (it != tune_cache().end()) {
+            Schedule s;
+            if (make_schedule(dev, cs, it->second.K, it->second.B, it->second.block, it->second.lds, s)) return s;
+            trace("autotune: cached K=%d B=%d block=%d does not fit this batch; re-tuning", it->second.K,
+                  it->second.B, it->second.block);
+        }
     }
     // Bounded sample: a prefix of every cone, about 2e11 gate evaluations in total.
     const double budget = 2e11;
@@ -73,6 +82,18 @@ Schedule autotune(Device& dev, const std::vector<Circuit*>& cs, const std::vecto
     double best_rate = -1;
     std::vector<uint64_t> b;
     double ms = 0;
+    // FASTLEC_ES_TUNE_FORCE="K,B,block" takes that candidate, when it fits, without timing
+    // (a test hook for schedule-dependent paths).
+    if (const char* f = std::getenv("FASTLEC_ES_TUNE_FORCE")) {
+        int fk = 0, fb = 0, fw = 0;
+        if (std::sscanf(f, "%d,%d,%d", &fk, &fb, &fw) == 3)
+            for (const Schedule& s : cands)
+                if (s.K == fk && s.B == fb && s.block == fw) {
+                    std::lock_guard<std::mutex> g(g_tune_mu);
+                    tune_cache()[key] = s;
+                    return s;
+                }
+    }
     run_interp(dev, cs, sample, cands[0], stream, nullptr, b, &ms);  // uploads programs, warms caches
     for (const Schedule& s : cands) {
         run_interp(dev, cs, sample, s, stream, nullptr, b, &ms);

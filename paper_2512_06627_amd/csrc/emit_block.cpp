@@ -19,6 +19,8 @@
 #include <algorithm>
 #include <cstdio>
 #include <map>
+#include <set>
+#include <climits>
 #include <sstream>
 
 #include "runtime.hpp"
@@ -74,11 +76,106 @@ struct Pool {
 
 uint64_t key_of(const LutRef& r) { return ((uint64_t)r.kind << 32) | r.index; }
 
+// Order of the body: the program's own order, except that a step whose operands are not yet
+// `dist` instructions old gives way to the next step that is ready.  The program's order
+// (depth first, chosen for few live values) puts a gate right after its fan-ins; a wave
+// then waits out the VALU latency on every step, which two or four waves per SIMD cannot
+// hide.  Outputs are folded into the miter word two at a time.
+std::vector<LutStep> schedule(const LutProgram& lp, int dist) {
+    std::vector<LutStep> in;
+    const LutStep* pending = nullptr;
+    for (const LutStep& st : lp.steps) {
+        if (st.op != LutStep::Output) {
+            in.push_back(st);
+            continue;
+        }
+        if (!pending) {
+            pending = &st;
+            continue;
+        }
+        LutStep pr{};
+        pr.op = LutStep::Output;
+        pr.nleaves = 2;
+        pr.leaf[0] = pending->leaf[0];
+        pr.leaf[1] = st.leaf[0];
+        pr.table = (uint8_t)((pending->out_neg ? 1 : 0) | (st.out_neg ? 2 : 0));
+        in.push_back(pr);
+        pending = nullptr;
+    }
+    if (pending) {
+        LutStep one{};
+        one.op = LutStep::Output;
+        one.nleaves = 1;
+        one.leaf[0] = pending->leaf[0];
+        one.table = pending->out_neg ? 1 : 0;
+        in.push_back(one);
+    }
+    const size_t N = in.size();
+    if (dist <= 1) return in;
+    std::map<uint64_t, size_t> producer;
+    for (size_t i = 0; i < N; ++i) {
+        if (in[i].op == LutStep::Lut) producer[((uint64_t)LutRef::Varying << 32) | in[i].dst] = i;
+        if (in[i].op == LutStep::ScalarAnd) producer[((uint64_t)LutRef::Uniform << 32) | in[i].dst] = i;
+    }
+    std::vector<std::vector<size_t>> preds(N), succs(N);
+    for (size_t i = 0; i < N; ++i) {
+        const LutStep& st = in[i];
+        const uint32_t k = st.op == LutStep::ScalarAnd ? 2 : st.nleaves;
+        for (uint32_t j = 0; j < k; ++j) {
+            auto it = producer.find(((uint64_t)st.leaf[j].kind << 32) | st.leaf[j].index);
+            if (it == producer.end()) continue;
+            if (std::find(preds[i].begin(), preds[i].end(), it->second) == preds[i].end()) {
+                preds[i].push_back(it->second);
+                succs[it->second].push_back(i);
+            }
+        }
+    }
+    std::vector<size_t> waiting(N);
+    std::set<size_t> ready;
+    for (size_t i = 0; i < N; ++i) {
+        waiting[i] = preds[i].size();
+        if (!waiting[i]) ready.insert(i);
+    }
+    std::vector<int64_t> slot(N, -1);
+    int64_t last_out = -(int64_t)dist, cur = 0;
+    auto lat = [&](size_t p, size_t i) -> int64_t {
+        // scalar results feed the next instruction; vector results need `dist` slots
+        return in[p].op == LutStep::ScalarAnd ? 1 : (in[i].op == LutStep::ScalarAnd ? 1 : dist);
+    };
+    std::vector<LutStep> out;
+    out.reserve(N);
+    while (!ready.empty()) {
+        size_t pick = N, best = N;
+        int64_t best_t = INT64_MAX;
+        for (size_t i : ready) {
+            int64_t t = in[i].op == LutStep::Output ? last_out + dist : 0;
+            for (size_t p : preds[i]) t = std::max(t, slot[p] + lat(p, i));
+            if (t <= cur) {
+                pick = i;
+                break;
+            }
+            if (t < best_t) {
+                best_t = t;
+                best = i;
+            }
+        }
+        if (pick == N) pick = best;
+        ready.erase(pick);
+        slot[pick] = cur++;
+        if (in[pick].op == LutStep::Output) last_out = slot[pick];
+        out.push_back(in[pick]);
+        for (size_t q : succs[pick])
+            if (--waiting[q] == 0) ready.insert(q);
+    }
+    return out;
+}
+
 }  // namespace
 
 bool emit_block_body(const LutProgram& lp, int vgpr_limit, int sgpr_limit, int sgpr_base, int word_operand_limit,
-                     std::string* code, BlockStats* stats) {
+                     int dist, std::string* code, BlockStats* stats) {
     const uint32_t n = lp.num_inputs;
+    const std::vector<LutStep> steps = schedule(lp, dist);
     // ---- asm operand numbering ------------------------------------------------------------
     // %0 m (output), %1 low and %2 high word of the base half-word index, then the lane
     // inputs 5..min(n,11)-1, then plan-time words (VGPR operands) up to the limit.
@@ -101,9 +198,9 @@ bool emit_block_body(const LutProgram& lp, int vgpr_limit, int sgpr_limit, int s
     };
     // words read by LUTs or outputs, most-used first, become operands
     std::map<uint32_t, uint32_t> word_uses;
-    for (const LutStep& st : lp.steps) {
+    for (const LutStep& st : steps) {
         if (st.op == LutStep::ScalarAnd) continue;
-        const uint32_t k = st.op == LutStep::Lut ? st.nleaves : 1;
+        const uint32_t k = st.nleaves;
         for (uint32_t j = 0; j < k; ++j)
             if (st.leaf[j].kind == LutRef::Word) ++word_uses[st.leaf[j].index];
     }
@@ -122,18 +219,18 @@ bool emit_block_body(const LutProgram& lp, int vgpr_limit, int sgpr_limit, int s
     // ---- uses of every value ------------------------------------------------------------
     std::map<uint64_t, size_t> last;
     std::map<uint64_t, size_t> last_scalar;  // last step that reads the value on the scalar unit
-    for (size_t t = 0; t < lp.steps.size(); ++t) {
-        const LutStep& st = lp.steps[t];
-        const uint32_t k = st.op == LutStep::Lut ? st.nleaves : st.op == LutStep::ScalarAnd ? 2 : 1;
+    for (size_t t = 0; t < steps.size(); ++t) {
+        const LutStep& st = steps[t];
+        const uint32_t k = st.op == LutStep::ScalarAnd ? 2 : st.nleaves;
         for (uint32_t j = 0; j < k; ++j) {
             last[key_of(st.leaf[j])] = t;
             if (st.op == LutStep::ScalarAnd) last_scalar[key_of(st.leaf[j])] = t;
         }
     }
     std::map<uint64_t, std::vector<size_t>> uses;
-    for (size_t t = 0; t < lp.steps.size(); ++t) {
-        const LutStep& st = lp.steps[t];
-        const uint32_t k = st.op == LutStep::Lut ? st.nleaves : st.op == LutStep::ScalarAnd ? 2 : 1;
+    for (size_t t = 0; t < steps.size(); ++t) {
+        const LutStep& st = steps[t];
+        const uint32_t k = st.op == LutStep::ScalarAnd ? 2 : st.nleaves;
         for (uint32_t j = 0; j < k; ++j) uses[key_of(st.leaf[j])].push_back(t);
     }
 
@@ -248,8 +345,8 @@ bool emit_block_body(const LutProgram& lp, int vgpr_limit, int sgpr_limit, int s
         }
     };
     char buf[160];
-    for (size_t t = 0; t < lp.steps.size(); ++t) {
-        const LutStep& st = lp.steps[t];
+    for (size_t t = 0; t < steps.size(); ++t) {
+        const LutStep& st = steps[t];
         if (st.op == LutStep::ScalarAnd) {
             Loc x = locate(st.leaf[0], true, t);
             Loc y = locate(st.leaf[1], true, t);
@@ -269,7 +366,7 @@ bool emit_block_body(const LutProgram& lp, int vgpr_limit, int sgpr_limit, int s
             if (!last.count(key_of(self))) release(self, t);
             continue;
         }
-        const uint32_t k = st.op == LutStep::Lut ? st.nleaves : 1;
+        const uint32_t k = st.nleaves;
         Loc src[3];
         for (uint32_t j = 0; j < k; ++j) src[j] = locate(st.leaf[j], false, t);
         // At most one distinct SGPR per VALU instruction.  A wave-uniform value that already
@@ -314,14 +411,16 @@ bool emit_block_body(const LutProgram& lp, int vgpr_limit, int sgpr_limit, int s
             where[key_of(self)] = d;
             if (!last.count(key_of(self))) release(self, t);
         } else {
-            // m = m | (x ^ neg): table over (m, x, x)
+            // m = m | (x ^ neg_x) | (y ^ neg_y): table over (m, x, y); a single output repeats x
+            const bool two = k == 2;
             uint8_t table = 0;
             for (uint32_t idx = 0; idx < 8; ++idx) {
-                const uint32_t mm = (idx >> 2) & 1u, x = (idx >> 1) & 1u;
-                if (mm | (x ^ (st.out_neg ? 1u : 0u))) table |= (uint8_t)(1u << idx);
+                const uint32_t mm = (idx >> 2) & 1u, x = (idx >> 1) & 1u, y = idx & 1u;
+                const uint32_t tx = x ^ (st.table & 1u), ty = two ? (y ^ ((st.table >> 1) & 1u)) : tx;
+                if (mm | tx | ty) table |= (uint8_t)(1u << idx);
             }
-            const std::string s = loc_text(src[0]);
-            std::snprintf(buf, sizeof buf, "v_bitop3_b32 %%0, %%0, %s, %s bitop3:0x%02x", s.c_str(), s.c_str(), table);
+            const std::string x = loc_text(src[0]), y = loc_text(src[two ? 1 : 0]);
+            std::snprintf(buf, sizeof buf, "v_bitop3_b32 %%0, %%0, %s, %s bitop3:0x%02x", x.c_str(), y.c_str(), table);
             line(buf);
             ++n_valu;
         }

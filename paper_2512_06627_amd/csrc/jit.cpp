@@ -94,18 +94,20 @@ std::string jit_source(const LutProgram& lp, int waves_per_eu, int block) {
          "    if (cancel && __builtin_amdgcn_readfirstlane(__hip_atomic_load(cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))) break;\n"
          "    const u64 hw0 = hw_first + item * tile_hw;\n"
          "    const u64 hw_stop = hw0 + tile_hw < hw_end ? hw0 + tile_hw : hw_end;\n"
+         "    const u64 b_first = __hip_atomic_load(best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);\n"
+         "    u64 best_seen = ((u64)__builtin_amdgcn_readfirstlane((u32)(b_first >> 32)) << 32) |\n"
+         "                    __builtin_amdgcn_readfirstlane((u32)b_first);\n"
          "    for (u64 base = hw0; base < hw_stop; base += " << 64 * P << ") {\n"
-         "      const u64 b_raw = __hip_atomic_load(best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);\n"
-         "      const u64 best_now = ((u64)__builtin_amdgcn_readfirstlane((u32)(b_raw >> 32)) << 32) |\n"
-         "                           __builtin_amdgcn_readfirstlane((u32)b_raw);\n"
-         "      if (32ull * base >= best_now) break;\n";
+         "      if (32ull * base >= best_seen) break;\n"
+         "      // read for the next pass: the load completes while this pass runs\n"
+         "      const u64 b_next = __hip_atomic_load(best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);\n";
     std::string block_body;
     if (P == 1 && specialized_emit_mode() == 1) {
-        // The compiler keeps its own values (claims, bounds, pointers, the ballot) in the
-        // registers that the block leaves alone: about 32 VGPRs and 30 SGPRs.
-        const int vgpr_budget = (waves_per_eu >= 4 ? 512 / waves_per_eu : 256) - 32;
+        // The compiler keeps its own values (claims, bounds, pointers, lane masks, words, the
+        // ballot) in the registers that the block leaves alone: about 24 VGPRs and 30 SGPRs.
+        const int vgpr_budget = std::min(256, 512 / waves_per_eu / 8 * 8) - 24;
         BlockStats bs;
-        if (!emit_block_body(lp, vgpr_budget, 64, 0, 20, &block_body, &bs)) {
+        if (!emit_block_body(lp, vgpr_budget, 64, 0, 20, specialized_latency_slots(), &block_body, &bs)) {
             block_body.clear();
             o << "      // one asm block would need " << bs.vgprs << " VGPRs and " << bs.sgprs << " SGPRs\n";
         }
@@ -245,6 +247,8 @@ std::string jit_source(const LutProgram& lp, int waves_per_eu, int block) {
          "        atomicMin(best, p);\n"
          "        break;\n"
          "      }\n"
+         "      best_seen = ((u64)__builtin_amdgcn_readfirstlane((u32)(b_next >> 32)) << 32) |\n"
+         "                  __builtin_amdgcn_readfirstlane((u32)b_next);\n"
          "    }\n"
          "  }\n"
          "}\n";
@@ -299,9 +303,10 @@ int env_int(const char* name, int dflt, int lo, int hi) {
 }
 }  // namespace
 
-int specialized_emit_mode() { return env_int("FASTLEC_ES_JIT_EMIT", 0, 0, 1); }
-int specialized_waves_per_eu() { return env_int("FASTLEC_ES_JIT_WAVES", 2, 1, 8); }
-int specialized_scalar_policy() { return env_int("FASTLEC_ES_JIT_SCALAR", 0, 0, 2); }
+int specialized_latency_slots() { return env_int("FASTLEC_ES_JIT_DIST", 1, 1, 64); }
+int specialized_emit_mode() { return env_int("FASTLEC_ES_JIT_EMIT", 1, 0, 1); }
+int specialized_waves_per_eu() { return env_int("FASTLEC_ES_JIT_WAVES", 3, 1, 8); }
+int specialized_scalar_policy() { return env_int("FASTLEC_ES_JIT_SCALAR", 2, 0, 2); }
 int specialized_block() {
     const int b = env_int("FASTLEC_ES_JIT_BLOCK", 256, 64, 1024);
     return b % 64 ? 256 : b;

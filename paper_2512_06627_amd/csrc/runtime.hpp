@@ -143,8 +143,10 @@ struct BlockStats {
     int vgprs = 0, sgprs = 0, word_operands = 0;
     uint32_t valu = 0, salu = 0, copies = 0, spills = 0;
 };
+// dist: slots between a VALU result and its first reader that the scheduler aims for.
 bool emit_block_body(const LutProgram& lp, int vgpr_limit, int sgpr_limit, int sgpr_base, int word_operand_limit,
-                     std::string* code, BlockStats* stats);
+                     int dist, std::string* code, BlockStats* stats);
+int specialized_latency_slots();  // FASTLEC_ES_JIT_DIST
 int specialized_emit_mode();  // FASTLEC_ES_JIT_EMIT: 1 one asm block per pass, 0 one asm statement per gate
 int jit_passes(const LutProgram& lp);
 

@@ -19,9 +19,13 @@ import paper_2512_06627_amd as es
 M32 = np.uint64(0xFFFFFFFF)
 
 
-@pytest.fixture(autouse=True)
-def block_emitter(monkeypatch):
+@pytest.fixture(autouse=True, params=["0", "2"], ids=["scalar-unit", "all-valu"])
+def block_emitter(monkeypatch, request):
+    """Both mappings: wave-uniform gates on the scalar unit (policy 0) and all gates in VALU
+    LUTs (policy 2), with the latency scheduler on."""
     monkeypatch.setenv("FASTLEC_ES_JIT_EMIT", "1")
+    monkeypatch.setenv("FASTLEC_ES_JIT_SCALAR", request.param)
+    monkeypatch.setenv("FASTLEC_ES_JIT_DIST", "6")
 
 
 def parse_block(src):

@@ -229,3 +229,26 @@ def test_batch_graph_replays_match_eager():
         assert [r["cex"] if r["verdict"] else None for r in res] == eager
     res = es.fastlec_es_check_batch(circs, kernel="interp_hbm")
     assert [r["cex"] if r["verdict"] else None for r in res] == eager
+
+
+def test_cached_schedule_refits_larger_batch(monkeypatch):
+    """A tuned schedule is cached per (rows, cones, work) bucket.  When a later batch in the same
+    bucket has larger value files, the cached workgroup may not fit in LDS any more; the cached
+    choice must be re-fitted (or re-tuned), never launched as is.  The hook forces the choice
+    K=4, B=8, 128 threads, which fits about 80 rows."""
+    monkeypatch.setenv("FASTLEC_ES_TUNE_FORCE", "4,8,128")
+    rng = miters.SplitMix64(78)
+    picked = []
+    for i in range(80):
+        size = rng.between(1100, 2000)
+        g = miters.layered_cone_miter(7000 + i, 10, size, fault_seed=(i if i % 3 == 0 else None))
+        c = es.fastlec_es_load_aig(g.to_aig())
+        info = c.info()
+        if 2048 <= info["num_ands_tfi"] < 4096:
+            picked.append((10 + info["peak_live_slots"] + 2, g, c))
+    picked.sort(key=lambda t: t[0])
+    assert picked[0][0] <= 70 and picked[-1][0] >= 84
+    for rows, g, c in picked:
+        print("batch of one cone, rows", rows, flush=True)
+        res = es.fastlec_es_check_batch([c])
+        assert (res[0]["cex"] if res[0]["verdict"] else None) == oracle.check(g.to_aag(), threads=8), rows
