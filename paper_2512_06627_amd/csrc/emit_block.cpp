@@ -72,6 +72,21 @@ struct Pool {
         free.push_back(r);
         std::sort(free.begin(), free.end(), std::greater<int>());
     }
+    // Lowest free register whose bank (number mod 4) is not in `avoid` (bit per bank); a new
+    // register otherwise, skipping at most three numbers (they stay free for later).
+    int take_bank(unsigned avoid) {
+        if (avoid == 0 || avoid == 15) return take();
+        for (size_t i = free.size(); i-- > 0;) {
+            const int r = free[i];
+            if (!((avoid >> (r & 3)) & 1u)) {
+                free.erase(free.begin() + (long)i);
+                high = std::max(high, r + 1);
+                return r;
+            }
+        }
+        while ((avoid >> (next & 3)) & 1u) give(next++);
+        return take();
+    }
 };
 
 uint64_t key_of(const LutRef& r) { return ((uint64_t)r.kind << 32) | r.index; }
@@ -173,7 +188,7 @@ std::vector<LutStep> schedule(const LutProgram& lp, int dist) {
 }  // namespace
 
 bool emit_block_body(const LutProgram& lp, int vgpr_limit, int sgpr_limit, int sgpr_base, int word_operand_limit,
-                     int dist, std::string* code, BlockStats* stats) {
+                     int dist, bool bank_aware, std::string* code, BlockStats* stats) {
     const uint32_t n = lp.num_inputs;
     const std::vector<LutStep> steps = schedule(lp, dist);
     // ---- asm operand numbering ------------------------------------------------------------
@@ -399,7 +414,23 @@ bool emit_block_body(const LutProgram& lp, int vgpr_limit, int sgpr_limit, int s
         for (uint32_t j = 0; j < k; ++j) release(st.leaf[j], t);
         for (int tv : temps) vp.give(tv);
         if (st.op == LutStep::Lut) {
-            Loc d{Kind::Vgpr, vp.take(), 0};
+            // Bank choice: avoid the banks of the operands that this value's first reader
+            // already has in VGPRs (three operands in one bank read serially).
+            unsigned avoid = 0;
+            if (bank_aware) {
+                LutRef self{LutRef::Varying, st.dst};
+                auto u = uses.find(key_of(self));
+                if (u != uses.end() && !u->second.empty()) {
+                    const LutStep& rd = steps[u->second.front()];
+                    const uint32_t rk = rd.op == LutStep::ScalarAnd ? 2 : rd.nleaves;
+                    for (uint32_t j = 0; j < rk; ++j) {
+                        if (rd.leaf[j].kind == self.kind && rd.leaf[j].index == self.index) continue;
+                        auto w = where.find(key_of(rd.leaf[j]));
+                        if (w != where.end() && w->second.kind == Kind::Vgpr) avoid |= 1u << (w->second.reg & 3);
+                    }
+                }
+            }
+            Loc d{Kind::Vgpr, vp.take_bank(avoid), 0};
             const std::string s0 = loc_text(src[0]);
             const std::string s1 = loc_text(src[k >= 2 ? 1 : 0]);
             const std::string s2 = loc_text(src[k >= 3 ? 2 : (k >= 2 ? 1 : 0)]);

@@ -107,7 +107,8 @@ std::string jit_source(const LutProgram& lp, int waves_per_eu, int block) {
         // ballot) in the registers that the block leaves alone: about 24 VGPRs and 30 SGPRs.
         const int vgpr_budget = std::min(256, 512 / waves_per_eu / 8 * 8) - 24;
         BlockStats bs;
-        if (!emit_block_body(lp, vgpr_budget, 64, 0, 20, specialized_latency_slots(), &block_body, &bs)) {
+        if (!emit_block_body(lp, vgpr_budget, 64, 0, 20, specialized_latency_slots(), specialized_bank_aware() != 0,
+                             &block_body, &bs)) {
             block_body.clear();
             o << "      // one asm block would need " << bs.vgprs << " VGPRs and " << bs.sgprs << " SGPRs\n";
         }
@@ -304,6 +305,7 @@ int env_int(const char* name, int dflt, int lo, int hi) {
 }  // namespace
 
 int specialized_latency_slots() { return env_int("FASTLEC_ES_JIT_DIST", 1, 1, 64); }
+int specialized_bank_aware() { return env_int("FASTLEC_ES_JIT_BANKS", 0, 0, 1); }
 int specialized_emit_mode() { return env_int("FASTLEC_ES_JIT_EMIT", 1, 0, 1); }
 int specialized_waves_per_eu() { return env_int("FASTLEC_ES_JIT_WAVES", 3, 1, 8); }
 int specialized_scalar_policy() { return env_int("FASTLEC_ES_JIT_SCALAR", 2, 0, 2); }

@@ -232,15 +232,47 @@ LutProgram make_lut_program(const Aig& g, const Plan& plan, int scalar_policy) {
         best_af[v] = out.empty() ? 1.0 : out[0].af;
     }
     // ---- 3. cover: gates needed by the outputs through their chosen cuts --------------
-    std::vector<uint8_t> required(V + 1, 0);
-    for (uint32_t o : g.outputs)
-        if (varying[o >> 1] == 1) required[o >> 1] = 1;
-    for (auto it = plan.order.rbegin(); it != plan.order.rend(); ++it) {
-        const uint32_t v = n + 1 + *it;
-        if (!required[v]) continue;
-        for (uint64_t q : cuts[v][0].keys)
-            if (q < (1ull << 40)) required[(uint32_t)q] = 1;
+    // Area flow picks cuts[v][0]; exact-area recovery then revisits every gate of the cover
+    // in topological order and keeps the cut that adds the fewest LUTs given the rest of
+    // the cover (reference counts over the chosen cuts), two rounds.
+    std::vector<uint32_t> sel(V + 1, 0), ref(V + 1, 0);
+    std::function<uint32_t(uint32_t, const Cut&)> ref_cut, deref_cut;
+    ref_cut = [&](uint32_t, const Cut& c) {
+        uint32_t a = 1;
+        for (uint64_t q : c.keys)
+            if (q < (1ull << 40) && ref[(uint32_t)q]++ == 0) a += ref_cut((uint32_t)q, cuts[(uint32_t)q][sel[(uint32_t)q]]);
+        return a;
+    };
+    deref_cut = [&](uint32_t, const Cut& c) {
+        uint32_t a = 1;
+        for (uint64_t q : c.keys)
+            if (q < (1ull << 40) && --ref[(uint32_t)q] == 0) a += deref_cut((uint32_t)q, cuts[(uint32_t)q][sel[(uint32_t)q]]);
+        return a;
+    };
+    for (uint32_t o : g.outputs) {
+        const uint32_t v = o >> 1;
+        if (varying[v] == 1 && ref[v]++ == 0) ref_cut(v, cuts[v][sel[v]]);
     }
+    for (int round = 0; round < 2; ++round) {
+        for (uint32_t k : plan.order) {
+            const uint32_t v = n + 1 + k;
+            if (varying[v] != 1 || ref[v] == 0) continue;
+            deref_cut(v, cuts[v][sel[v]]);
+            uint32_t best = sel[v], best_area = UINT32_MAX;
+            for (uint32_t i = 0; i < cuts[v].size(); ++i) {
+                const uint32_t a = ref_cut(v, cuts[v][i]);
+                deref_cut(v, cuts[v][i]);
+                if (a < best_area) {
+                    best_area = a;
+                    best = i;
+                }
+            }
+            sel[v] = best;
+            ref_cut(v, cuts[v][best]);
+        }
+    }
+    std::vector<uint8_t> required(V + 1, 0);
+    for (uint32_t v = 0; v <= V; ++v) required[v] = ref[v] > 0 && varying[v] == 1;
     // uniform values actually read (by required LUTs, by outputs or by other scalar steps)
     std::vector<uint8_t> scalar_needed(V + 1, 0);
     std::map<uint32_t, uint32_t> var_of_uniform;  // uniform value id -> AIG var
@@ -257,7 +289,7 @@ LutProgram make_lut_program(const Aig& g, const Plan& plan, int scalar_policy) {
     };
     for (uint32_t v = 0; v <= V; ++v)
         if (required[v])
-            for (uint64_t q : cuts[v][0].keys)
+            for (uint64_t q : cuts[v][sel[v]].keys)
                 if (q >= (1ull << 40)) need_ref(ref_of_key[q]);
     for (uint32_t o : g.outputs)
         if (varying[o >> 1] != 1) need_ref(val[o >> 1].ref);
@@ -287,7 +319,7 @@ LutProgram make_lut_program(const Aig& g, const Plan& plan, int scalar_policy) {
         const uint32_t v = n + 1 + k;
         if (varying[v] == 1) ++total_varying;
         if (varying[v] != 1 || !required[v]) continue;
-        const Cut& c = cuts[v][0];
+        const Cut& c = cuts[v][sel[v]];
         LutStep st{};
         st.op = LutStep::Lut;
         st.nleaves = (uint8_t)c.keys.size();

@@ -144,8 +144,10 @@ struct BlockStats {
     uint32_t valu = 0, salu = 0, copies = 0, spills = 0;
 };
 // dist: slots between a VALU result and its first reader that the scheduler aims for.
+// bank_aware: place a LUT result in a VGPR bank other than its first reader's other operands.
 bool emit_block_body(const LutProgram& lp, int vgpr_limit, int sgpr_limit, int sgpr_base, int word_operand_limit,
-                     int dist, std::string* code, BlockStats* stats);
+                     int dist, bool bank_aware, std::string* code, BlockStats* stats);
+int specialized_bank_aware();     // FASTLEC_ES_JIT_BANKS
 int specialized_latency_slots();  // FASTLEC_ES_JIT_DIST
 int specialized_emit_mode();  // FASTLEC_ES_JIT_EMIT: 1 one asm block per pass, 0 one asm statement per gate
 int jit_passes(const LutProgram& lp);

@@ -19,13 +19,16 @@ import paper_2512_06627_amd as es
 M32 = np.uint64(0xFFFFFFFF)
 
 
-@pytest.fixture(autouse=True, params=["0", "2"], ids=["scalar-unit", "all-valu"])
+@pytest.fixture(autouse=True, params=[("0", "6", "0"), ("2", "1", "0"), ("2", "6", "1")],
+                ids=["scalar-unit", "all-valu", "all-valu-spaced-banks"])
 def block_emitter(monkeypatch, request):
-    """Both mappings: wave-uniform gates on the scalar unit (policy 0) and all gates in VALU
-    LUTs (policy 2), with the latency scheduler on."""
+    """Mappings and emitter options: wave-uniform gates on the scalar unit (policy 0) or all
+    gates in VALU LUTs (policy 2); latency spacing; bank-aware VGPR choice."""
+    policy, dist, banks = request.param
     monkeypatch.setenv("FASTLEC_ES_JIT_EMIT", "1")
-    monkeypatch.setenv("FASTLEC_ES_JIT_SCALAR", request.param)
-    monkeypatch.setenv("FASTLEC_ES_JIT_DIST", "6")
+    monkeypatch.setenv("FASTLEC_ES_JIT_SCALAR", policy)
+    monkeypatch.setenv("FASTLEC_ES_JIT_DIST", dist)
+    monkeypatch.setenv("FASTLEC_ES_JIT_BANKS", banks)
 
 
 def parse_block(src):
