@@ -30,6 +30,22 @@ PEAK_WAVE_INSTR = PEAK_LANE_OPS / 64                     # 1.23e12 wave64 VALU i
 PEAK_NODE_PATTERNS = PEAK_LANE_OPS * 32                   # 2.52e15 AND-node*patterns/s
 
 
+# HBM bytes per launch of the 16x16 miter's specialized kernel, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (each scaled by what the counter reads for a device copy of known size; summary
+# and commands in profiles/es_specialized_mult16_counters.md).  Valid only for the kernel whose
+# generated source has this SHA-256; any other kernel reports null.
+PROFILED_TRAFFIC = {"source_sha256": "7fef964a992de86123a3066d7bd2973be47ef93ec370f72adb88c2d889156045",
+                    "bytes_per_launch": 7587323}
+
+
+def profiled_traffic(es, c):
+    import hashlib
+    src = es.fastlec_es_specialized_source(c, 3)
+    if PROFILED_TRAFFIC["source_sha256"] == hashlib.sha256(src.encode()).hexdigest():
+        return PROFILED_TRAFFIC["bytes_per_launch"]
+    return None
+
+
 def executed_view(es, c, n, num_ands, kernel_s):
     """Instructions the specialized kernel executes per 2,048-pattern pass (from its generated
     body), and the VALU issue rate they imply."""
@@ -114,10 +130,11 @@ def batch_leg(es, stream, seed: int = 4, count: int = 256, faulty: int = 26, n_r
 def serve_leg(es, stream, seed: int = 5, seconds: float = 30.0, max_requests: int = 400,
               pool: int = 40, budget_gib: int = 64, load: float = 0.7):
     """Poisson stream of cones (n ~ U{16..34}, ~U[500, 20000] AND gates, 10% faulty) served by
-    continuous batching with an HBM budget.  Capacity is measured on the same server first (every
-    pool cone submitted at once; work = gates x patterns each job actually evaluated), and the
-    arrival rate is set to `load` of it.  Reports p50/p99 latency and checks every answer against
-    the same cone checked alone."""
+    continuous batching with an HBM budget; large jobs move to their specialized kernel once it is
+    compiled.  Capacity is measured on the same server first (every pool cone submitted at once;
+    work = gates x patterns each job actually evaluated), and the arrival rate is set to `load` of
+    it.  Reports p50/p90/p99 latency and checks every answer against the same cone checked
+    alone."""
     import miters
     rng = miters.SplitMix64(seed)
     t0 = time.perf_counter()
@@ -169,6 +186,7 @@ def serve_leg(es, stream, seed: int = 5, seconds: float = 30.0, max_requests: in
             "node_patterns_per_s": done_work / wall, "max_jobs_in_flight": st["max_active"],
             "peak_charge_bytes": st["peak_charge_bytes"], "budget_bytes": st["budget_bytes"],
             "server_device_bytes": st["device_bytes"], "steps": st["steps"] - steps0,
+            "specialized_slices": st["specialized_slices"], "latency_ms_p90": q(0.90), "latency_ms_max": lat[-1],
             "each_equal_alone": served == [alone[k] for k in which], "pool": pool, "generate_s": gen_s}
 
 
@@ -249,7 +267,8 @@ def main():
                                f"equivalent (all patterns simulated)",
                    "kernel": a.kernel, "peak_live_slots": info["peak_live_slots"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_NODE_PATTERNS,
-                     "unit": "node*patterns/s", "frac": achieved / PEAK_NODE_PATTERNS, "traffic": None,
+                     "unit": "node*patterns/s", "frac": achieved / PEAK_NODE_PATTERNS,
+                     "traffic": profiled_traffic(es, c) if a.kernel == "specialized" else None,
                      "kernel_ms_median": k_ms,
                      "note": "peak = 256 CU * 128 int32 lanes/cycle * 2.4 GHz * 32 patterns per lane-op "
                              "(one lane-op per AND gate); achieved = N*2^n / mean kernel time (HIP events); "

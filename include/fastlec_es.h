@@ -143,6 +143,7 @@ typedef struct {
     uint64_t device_bytes;               /* device memory the server actually holds (tables, value files) */
     uint64_t max_active;                 /* most jobs in flight at once so far */
     double busy_ms;                      /* summed device time of the step kernels */
+    uint64_t specialized_slices;         /* job slices run on a job's specialized kernel */
 } fastlec_es_server_stats;
 
 /* Start a serving loop on opts->device (continuous batching).  Submitted jobs wait in a
@@ -153,8 +154,11 @@ typedef struct {
  * over the next slice of every job in flight, so jobs that arrive while others run share
  * the device with them; a job retires as soon as its answer is final (all patterns clean,
  * or the lowest failing pattern known).  Job descriptors and best-so-far values stay in a
- * device-resident job table between steps.  opts: device, stream, schedule fields; the
- * word range, deadline and cancel fields are ignored.  budget_bytes > 0. */
+ * device-resident job table between steps.  A job whose remaining interpreter time is
+ * estimated well above the time to compile its specialized kernel is compiled on a
+ * background thread meanwhile; its later slices run on that kernel (same ascending slices,
+ * same answer).  FASTLEC_ES_SERVER_JIT=0 turns this off.  opts: device, stream, schedule
+ * fields; the word range, deadline and cancel fields are ignored.  budget_bytes > 0. */
 int fastlec_es_server_create(const fastlec_es_options *opts, size_t budget_bytes, fastlec_es_server **out);
 
 /* Queue a job; never blocks.  The circuit must stay alive until the job is polled done.

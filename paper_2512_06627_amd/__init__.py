@@ -77,7 +77,8 @@ class fastlec_es_server_stats(ctypes.Structure):
                 ("steps", ctypes.c_uint64), ("active", ctypes.c_uint64), ("queued", ctypes.c_uint64),
                 ("charge_in_use_bytes", ctypes.c_uint64), ("budget_bytes", ctypes.c_uint64),
                 ("peak_charge_bytes", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64),
-                ("max_active", ctypes.c_uint64), ("busy_ms", ctypes.c_double)]
+                ("max_active", ctypes.c_uint64), ("busy_ms", ctypes.c_double),
+                ("specialized_slices", ctypes.c_uint64)]
 
 
 # (name, restype, argtypes) of every symbol in include/fastlec_es.h

@@ -116,34 +116,20 @@ __global__ void __launch_bounds__(1024) es_interp_kernel(InterpLaunch L) {
                 *(V*)(col + (size_t)(1 + i) * kRowWords) = x;
             }
             V m = zero;
-            // The next bundle's instructions are fetched while this bundle's operands are
-            // being read, so the scalar-load and LDS latencies overlap.
-            Instr ins[B];
-            if (n_instr > 0) {  // streams are whole bundles; an empty stream reads nothing
+            for (uint32_t t = 0; t < n_instr; t += B) {
+                Instr ins[B];
 #pragma unroll
                 for (int u = 0; u < B; ++u) {
-                    ins[u].a = prog[u].a;
-                    ins[u].b = prog[u].b;
-                    ins[u].d = prog[u].d;
-                    ins[u].flags = prog[u].flags;
+                    ins[u].a = prog[t + u].a;
+                    ins[u].b = prog[t + u].b;
+                    ins[u].d = prog[t + u].d;
+                    ins[u].flags = prog[t + u].flags;
                 }
-            }
-            for (uint32_t t = 0; t < n_instr; t += B) {
                 V a[B], b[B];
 #pragma unroll
                 for (int u = 0; u < B; ++u) {
                     a[u] = *(const V*)(col + (size_t)(ins[u].a & kRowMask) * kRowWords);
                     b[u] = *(const V*)(col + (size_t)(ins[u].b & kRowMask) * kRowWords);
-                }
-                Instr nxt[B];
-                if (t + B < n_instr) {
-#pragma unroll
-                    for (int u = 0; u < B; ++u) {
-                        nxt[u].a = prog[t + B + u].a;
-                        nxt[u].b = prog[t + B + u].b;
-                        nxt[u].d = prog[t + B + u].d;
-                        nxt[u].flags = prog[t + B + u].flags;
-                    }
                 }
 #pragma unroll
                 for (int u = 0; u < B; ++u) {
@@ -158,8 +144,6 @@ __global__ void __launch_bounds__(1024) es_interp_kernel(InterpLaunch L) {
                         for (int j = 0; j < K; ++j) m.w[j] |= (r.w[j] & op) | (~r.w[j] & on);
                     }
                 }
-#pragma unroll
-                for (int u = 0; u < B; ++u) ins[u] = nxt[u];
             }
             // Lowest failing pattern of this pass: first sub-word j with a nonzero lane, then
             // its lowest lane l, then the lowest set bit of that lane's word.

@@ -305,7 +305,7 @@ int env_int(const char* name, int dflt, int lo, int hi) {
 }  // namespace
 
 int specialized_latency_slots() { return env_int("FASTLEC_ES_JIT_DIST", 1, 1, 64); }
-int specialized_bank_aware() { return env_int("FASTLEC_ES_JIT_BANKS", 0, 0, 1); }
+int specialized_bank_aware() { return env_int("FASTLEC_ES_JIT_BANKS", 1, 0, 1); }
 int specialized_emit_mode() { return env_int("FASTLEC_ES_JIT_EMIT", 1, 0, 1); }
 int specialized_waves_per_eu() { return env_int("FASTLEC_ES_JIT_WAVES", 3, 1, 8); }
 int specialized_scalar_policy() { return env_int("FASTLEC_ES_JIT_SCALAR", 2, 0, 2); }
@@ -353,41 +353,63 @@ std::shared_ptr<JitKernel> jit_kernel(Circuit& c, int waves_per_eu, double* comp
     return k;
 }
 
-void run_jit(Device& dev, Circuit& c, JitKernel& k, const HwRange& r, uint64_t tile_hw, hipStream_t stream,
-             const int* cancel, uint64_t* best_out, double* kernel_ms) {
-    (void)c;
-    hipFunction_t fn;
+JitLaunchPlan jit_prepare(Device& dev, JitKernel& k, const HwRange& r, uint64_t tile_hw) {
+    JitLaunchPlan lp;
     int blocks_per_cu;
     {
         std::lock_guard<std::mutex> g(k.mu);
         auto it = k.per_device.find(dev.ordinal);
         if (it == k.per_device.end()) {
             hipModule_t mod;
+            hipFunction_t fn;
             trace("specialized: loading module on device %d", dev.ordinal);
             FES_HIP(hipModuleLoadData(&mod, k.code.data()));
             FES_HIP(hipModuleGetFunction(&fn, mod, "fes_es_kernel"));
             int b = 0;
             FES_HIP(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, k.block, 0));
+            // The persistent grid holds the targeted waves per SIMD (a workgroup of `block`
+            // threads puts block/256 waves on each of the CU's four SIMDs), never more: the
+            // register count decides whether one more wave would fit, and at four waves per
+            // SIMD the 16x16 kernel runs a third slower than at three.
+            const int target = std::max(1, k.waves_per_eu * 4 * 64 / k.block);
             k.per_device[dev.ordinal] = {mod, fn};
-            k.blocks_per_cu[dev.ordinal] = std::max(1, b);
+            k.blocks_per_cu[dev.ordinal] = std::max(1, std::min(b, target));
         }
-        fn = k.per_device[dev.ordinal].second;
+        lp.fn = k.per_device[dev.ordinal].second;
         blocks_per_cu = k.blocks_per_cu[dev.ordinal];
     }
-    const int grid = dev.prop.multiProcessorCount * blocks_per_cu;
-    const uint64_t waves = (uint64_t)grid * (k.block / 64);
+    lp.grid = dev.prop.multiProcessorCount * blocks_per_cu;
+    lp.block = k.block;
+    const uint64_t waves = (uint64_t)lp.grid * (k.block / 64);
     const uint64_t step = 64ull * (uint64_t)k.passes;  // half-words per loop iteration
-    uint64_t hw_first = r.begin / step * step;
-    const uint64_t span = r.end - hw_first;
+    lp.hw_begin = r.begin;
+    lp.hw_end = r.end;
+    lp.hw_first = r.begin / step * step;
+    const uint64_t span = r.end - lp.hw_first;
     uint64_t tile = tile_hw;
     if (!tile) {
         uint64_t target = span / std::max<uint64_t>(1, waves * 16);
         tile = step;
         while (tile < target && tile < 64ull * 64) tile *= 2;
     }
-    tile = (tile + step - 1) / step * step;
-    uint64_t total_items = (span + tile - 1) / tile;
+    lp.tile = (tile + step - 1) / step * step;
+    lp.total_items = (span + lp.tile - 1) / lp.tile;
+    return lp;
+}
 
+void jit_enqueue(const JitLaunchPlan& lp, uint64_t* next_item, uint64_t* best, const int* cancel, hipStream_t stream) {
+    uint64_t hw_begin = lp.hw_begin, hw_end = lp.hw_end, hw_first = lp.hw_first, tile = lp.tile,
+             total_items = lp.total_items;
+    void* args[] = {&hw_begin, &hw_end, &hw_first, &tile, &total_items, &next_item, &best, &cancel};
+    trace("specialized launch: grid=%d block=%d items=%llu tile=%llu", lp.grid, lp.block,
+          (unsigned long long)lp.total_items, (unsigned long long)lp.tile);
+    FES_HIP(hipModuleLaunchKernel(lp.fn, lp.grid, 1, 1, lp.block, 1, 1, 0, stream, args, nullptr));
+}
+
+void run_jit(Device& dev, Circuit& c, JitKernel& k, const HwRange& r, uint64_t tile_hw, hipStream_t stream,
+             const int* cancel, uint64_t* best_out, double* kernel_ms) {
+    (void)c;
+    const JitLaunchPlan lp = jit_prepare(dev, k, r, tile_hw);
     Buffer buf = dev.acquire(4096);
     struct Releaser {
         Device& d;
@@ -400,8 +422,6 @@ void run_jit(Device& dev, Circuit& c, JitKernel& k, const HwRange& r, uint64_t t
     uint8_t* devp = (uint8_t*)buf.dev;
     uint64_t* next_item = (uint64_t*)devp;
     uint64_t* best = (uint64_t*)(devp + 64);
-    uint64_t hw_begin = r.begin, hw_end = r.end;
-    void* args[] = {&hw_begin, &hw_end, &hw_first, &tile, &total_items, &next_item, &best, &cancel};
     hipEvent_t e0, e1;
     FES_HIP(hipEventCreate(&e0));
     FES_HIP(hipEventCreate(&e1));
@@ -412,11 +432,9 @@ void run_jit(Device& dev, Circuit& c, JitKernel& k, const HwRange& r, uint64_t t
             (void)hipEventDestroy(b);
         }
     } ev{e0, e1};
-    trace("specialized launch: grid=%d block=%d items=%llu tile=%llu", grid, k.block,
-          (unsigned long long)total_items, (unsigned long long)tile);
     FES_HIP(hipMemcpyAsync(devp, host, 128, hipMemcpyHostToDevice, stream));
     FES_HIP(hipEventRecord(e0, stream));
-    FES_HIP(hipModuleLaunchKernel(fn, grid, 1, 1, k.block, 1, 1, 0, stream, args, nullptr));
+    jit_enqueue(lp, next_item, best, cancel, stream);
     FES_HIP(hipEventRecord(e1, stream));
     FES_HIP(hipMemcpyAsync(host + 8, best, 8, hipMemcpyDeviceToHost, stream));
     FES_HIP(hipStreamSynchronize(stream));

@@ -135,6 +135,16 @@ int specialized_scalar_policy();  // FASTLEC_ES_JIT_SCALAR: 0 all, 1 pure unifor
 std::shared_ptr<JitKernel> jit_kernel(Circuit& c, int waves_per_eu, double* compile_ms);
 void run_jit(Device& dev, Circuit& c, JitKernel& k, const HwRange& r, uint64_t tile_hw, hipStream_t stream,
              const int* cancel, uint64_t* best, double* kernel_ms);
+// The same launch in two parts, for callers that keep `best` and the claim counter in their
+// own device memory (the server): the grid and tiling of range r, then the launch alone.
+// *next_item must be zero when the kernel starts.
+struct JitLaunchPlan {
+    hipFunction_t fn = nullptr;
+    int grid = 0, block = 0;
+    uint64_t hw_begin = 0, hw_end = 0, hw_first = 0, tile = 0, total_items = 0;
+};
+JitLaunchPlan jit_prepare(Device& dev, JitKernel& k, const HwRange& r, uint64_t tile_hw);
+void jit_enqueue(const JitLaunchPlan& lp, uint64_t* next_item, uint64_t* best, const int* cancel, hipStream_t stream);
 std::string jit_source(const LutProgram& lp, int waves_per_eu, int block);
 
 // The per-pass body as one asm statement with planner-assigned registers (v0.., s<sgpr_base>..).

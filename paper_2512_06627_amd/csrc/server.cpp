@@ -13,6 +13,14 @@
 // kernels' atomicMin, read back after each step, reset when a slot is reused)
 // and the slot's descriptors, which the host refreshes each step with the
 // job's next slice.
+//
+// Specialized tier: pattern spaces differ by many orders of magnitude (2^n), so a
+// few large jobs carry most of the work.  A job whose remaining interpreter time is
+// estimated well above the cost of compiling its specialized kernel is handed to a
+// compile thread while it keeps running on the interpreter; from the step after the
+// kernel is ready, the job's slices run on the specialized kernel instead (same
+// ascending slices, same best[] entry, so the answer cannot change).  Circuits
+// submitted again reuse their compiled kernel at once.
 #include <algorithm>
 #include <cmath>
 #include <condition_variable>
@@ -39,6 +47,9 @@ struct Job {
     bool done = false;
     int status = FASTLEC_OK;
     fastlec_es_result res{};
+    bool compile_queued = false;     // handed to the compile thread
+    bool compiling = false;          // the compile thread is using the circuit
+    std::shared_ptr<JitKernel> jit;  // set when the specialized kernel is ready
 };
 
 uint64_t env_u64(const char* name, uint64_t dflt) {
@@ -78,6 +89,15 @@ struct fastlec_es_server {
     std::vector<uint32_t> free_slots;
     double rate = 1e14;  // node*patterns per second, running estimate
     std::thread th;
+    // specialized tier
+    int jit_mode = 1;        // 0 off, 1 by estimate, 2 every job (test hook)
+    double jit_rate = 2e15;  // node*patterns per second of the specialized kernel, estimate
+    size_t off_ctl_jit = 0;  // per-slot claim counters of specialized launches
+    std::deque<Job*> compile_queue;
+    std::condition_variable cv_compile;
+    std::thread compiler;
+    void compile_loop();
+    void plan_tiers(const std::vector<Job*>& act);
 
     uint64_t charge_of(const Circuit& c) const {
         const uint32_t n = c.plan1.num_inputs;
@@ -88,6 +108,66 @@ struct fastlec_es_server {
     void step(const std::vector<Job*>& act);
     void finish(Job* j, double now);
 };
+
+namespace {
+// The circuit's specialized kernel if it is already compiled.  Never compiles and never
+// waits: a kernel whose compile is in progress holds its lock and counts as not ready.
+std::shared_ptr<JitKernel> compiled_kernel(Circuit& c, int waves) {
+    std::lock_guard<std::mutex> g(c.mu);
+    auto it = c.jit.find(waves);
+    if (it == c.jit.end()) return nullptr;
+    std::unique_lock<std::mutex> gk(it->second->mu, std::try_to_lock);
+    if (!gk.owns_lock()) return nullptr;
+    return it->second->code.empty() ? nullptr : it->second;
+}
+}  // namespace
+
+void fastlec_es_server::compile_loop() {
+    for (;;) {
+        Job* j = nullptr;
+        {
+            std::unique_lock<std::mutex> g(mu);
+            cv_compile.wait(g, [&] { return stop || !compile_queue.empty(); });
+            if (stop) return;
+            j = compile_queue.front();
+            compile_queue.pop_front();
+            if (j->done) continue;
+            j->compiling = true;
+        }
+        std::shared_ptr<JitKernel> k;
+        try {
+            k = jit_kernel(*j->c, specialized_waves_per_eu(), nullptr);
+        } catch (...) {
+            k = nullptr;  // the job stays on the interpreter
+        }
+        std::lock_guard<std::mutex> g(mu);
+        j->compiling = false;
+        if (k && !j->done) j->jit = k;
+        cv_done.notify_all();
+    }
+}
+
+void fastlec_es_server::plan_tiers(const std::vector<Job*>& act) {
+    if (jit_mode == 0) return;
+    std::lock_guard<std::mutex> g(mu);
+    for (Job* j : act) {
+        if (j->jit || j->compile_queued) continue;
+        if (auto k = compiled_kernel(*j->c, specialized_waves_per_eu())) {
+            j->jit = k;
+            continue;
+        }
+        // Remaining interpreter time vs compile time (hipRTC takes about 0.2 ms per AND
+        // gate for these kernels; compiles run one at a time).
+        const double gates = std::max<uint32_t>(1, j->c->plan1.num_gate_instrs);
+        const double interp_s = 32.0 * gates * (double)(j->range.end - j->cursor) / rate;
+        const double compile_s = 0.3 + 2.5e-4 * gates;
+        if (jit_mode == 2 || interp_s > 2.0 * compile_s + 1.0) {
+            j->compile_queued = true;
+            compile_queue.push_back(j);
+            cv_compile.notify_one();
+        }
+    }
+}
 
 void fastlec_es_server::finish(Job* j, double now) {
     j->done = true;
@@ -103,16 +183,34 @@ void fastlec_es_server::finish(Job* j, double now) {
 void fastlec_es_server::step(const std::vector<Job*>& act) {
     // Slices: equal gate-evaluation budget per job, at least 16 passes.
     const uint32_t pass_hw = 64u * kK;
+    // Tier of every job for this step (the compile thread may set a kernel meanwhile).
+    std::vector<std::shared_ptr<JitKernel>> jk(act.size());
+    {
+        std::lock_guard<std::mutex> g(mu);
+        for (size_t t = 0; t < act.size(); ++t) jk[t] = act[t]->jit;
+    }
     const double target_np = rate * step_ms_target / 1e3;
-    const double per_job = target_np / (double)act.size();
+    size_t n_interp = 0;
+    for (auto& k : jk) n_interp += k ? 0 : 1;
+    const double per_job = target_np / (double)std::max<size_t>(1, n_interp);
     std::vector<Circuit*> lds_c, hbm_c;
     std::vector<HwRange> lds_r, hbm_r;
     std::vector<uint32_t> lds_i, hbm_i;
     const size_t lds_blk = dev->prop.sharedMemPerBlock ? dev->prop.sharedMemPerBlock : 65536;
     double step_np = 0;
     std::vector<HwRange> windows(act.size());
+    std::vector<size_t> jit_jobs;
     for (size_t t = 0; t < act.size(); ++t) {
         Job* j = act[t];
+        if (jk[t]) {  // specialized slice: about one step's worth at the kernel's rate
+            const double per_hw = 32.0 * std::max<uint32_t>(1, j->c->plan1.num_gate_instrs);
+            const uint64_t step_hw = 64ull * (uint64_t)jk[t]->passes;
+            uint64_t slice = (uint64_t)std::max(64.0 * (double)step_hw, std::floor(jit_rate * step_ms_target / 1e3 / per_hw));
+            slice = (slice + step_hw - 1) / step_hw * step_hw;
+            windows[t] = HwRange{j->cursor, std::min(j->range.end, j->cursor + slice)};
+            jit_jobs.push_back(t);
+            continue;
+        }
         const Plan& p = j->c->plan_for(kB);
         const double per_hw = 32.0 * std::max<size_t>(1, p.prog.size());
         uint64_t slice = (uint64_t)std::max(16.0 * pass_hw, std::floor(per_job / per_hw));
@@ -179,22 +277,45 @@ void fastlec_es_server::step(const std::vector<Job*>& act) {
         FES_HIP(launch_interp(L, g.sch.K, g.sch.B, g.sch.lds, g.sch.grid, g.sch.block, stream));
     }
     FES_HIP(hipEventRecord(e1, stream));
+    // Specialized slices: own claim counter per slot (zeroed first), shared best[] entry.
+    hipEvent_t e2 = nullptr;
+    double jit_np = 0;
+    if (!jit_jobs.empty()) {
+        uint64_t* hc = (uint64_t*)(host + off_ctl_jit);
+        for (size_t t : jit_jobs) {
+            Job* j = act[t];
+            hc[j->slot] = 0;
+            FES_HIP(hipMemcpyAsync(devp + off_ctl_jit + 8ull * j->slot, &hc[j->slot], 8, hipMemcpyHostToDevice, stream));
+            const JitLaunchPlan lp = jit_prepare(*dev, *jk[t], windows[t], 0);
+            jit_enqueue(lp, (uint64_t*)(devp + off_ctl_jit + 8ull * j->slot), (uint64_t*)(devp + off_best + 8ull * j->slot),
+                        nullptr, stream);
+            jit_np += 32.0 * std::max<uint32_t>(1, j->c->plan1.num_gate_instrs) * (double)(windows[t].end - windows[t].begin);
+        }
+        FES_HIP(hipEventCreate(&e2));
+        FES_HIP(hipEventRecord(e2, stream));
+    }
     FES_HIP(hipMemcpyAsync(host + off_best, devp + off_best, 8ull * kCapacity, hipMemcpyDeviceToHost, stream));
     FES_HIP(hipStreamSynchronize(stream));
-    float ms = 0;
+    float ms = 0, jit_ms = 0;
     FES_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (e2) {
+        FES_HIP(hipEventElapsedTime(&jit_ms, e1, e2));
+        (void)hipEventDestroy(e2);
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (ms > 0.5f) rate = 0.7 * rate + 0.3 * (step_np / (ms / 1e3));
+    if (n_interp && ms > 0.5f) rate = 0.7 * rate + 0.3 * (step_np / (ms / 1e3));
+    if (jit_np > 0 && jit_ms > 0.5f) jit_rate = 0.7 * jit_rate + 0.3 * (jit_np / (jit_ms / 1e3));
 
     const uint64_t* best = (const uint64_t*)(host + off_best);
     const double now = now_ms();
     std::lock_guard<std::mutex> g(mu);
     st.steps++;
-    st.busy_ms += ms;
+    st.busy_ms += ms + jit_ms;
+    st.specialized_slices += jit_jobs.size();
     for (size_t t = 0; t < act.size(); ++t) {
         Job* j = act[t];
-        j->kernel_ms += ms;
+        j->kernel_ms += jk[t] ? jit_ms / (double)jit_jobs.size() : ms;
         const uint64_t b = best[j->slot];
         const uint32_t n = j->c->plan1.num_inputs;
         if (b != ~0ull) {
@@ -263,6 +384,7 @@ void fastlec_es_server::loop() {
                 hb[s] = ~0ull;
                 FES_HIP(hipMemcpyAsync((uint8_t*)table.dev + off_best + 8ull * s, &hb[s], 8, hipMemcpyHostToDevice, stream));
             }
+            plan_tiers(act);
             step(act);
         }
     } catch (const Error& e) {
@@ -308,13 +430,16 @@ int fastlec_es_server_create(const fastlec_es_options* opts, size_t budget_bytes
         s->step_ms_target = (double)std::max<uint64_t>(1, env_u64("FASTLEC_ES_SERVER_STEP_MS", 10));
         s->dev = &device(s->opts.device);
         s->stream = s->opts.hip_stream ? (hipStream_t)s->opts.hip_stream : s->dev->stream;
+        s->jit_mode = (int)std::min<uint64_t>(2, env_u64("FASTLEC_ES_SERVER_JIT", 1));
         s->off_desc_lds = (s->off_best + 8ull * kCapacity + 255) & ~size_t(255);
         s->off_desc_hbm = s->off_desc_lds + sizeof(ConeDesc) * kCapacity;
-        s->table = s->dev->acquire(s->off_desc_hbm + sizeof(ConeDesc) * kCapacity);
+        s->off_ctl_jit = (s->off_desc_hbm + sizeof(ConeDesc) * kCapacity + 255) & ~size_t(255);
+        s->table = s->dev->acquire(s->off_ctl_jit + 8ull * kCapacity);
         for (uint32_t i = kCapacity; i-- > 0;) s->free_slots.push_back(i);
         s->st.budget_bytes = budget_bytes;
         fastlec_es_server* raw = s.get();
         s->th = std::thread([raw] { raw->loop(); });
+        s->compiler = std::thread([raw] { raw->compile_loop(); });
         *out = s.release();
         return FASTLEC_OK;
     } catch (const Error& e) {
@@ -355,12 +480,13 @@ int fastlec_es_server_poll(fastlec_es_server* s, uint64_t ticket, fastlec_es_res
     auto it = s->jobs.find(ticket);
     if (it == s->jobs.end()) return FASTLEC_ERR_INVALID;
     Job* j = it->second.get();
-    if (!j->done) {
+    if (!j->done || j->compiling) {  // a compile in progress still reads the circuit
         if (!wait) return 0;
-        s->cv_done.wait(g, [&] { return j->done; });
+        s->cv_done.wait(g, [&] { return j->done && !j->compiling; });
     }
     *out = j->res;
     const int status = j->status;
+    s->compile_queue.erase(std::remove(s->compile_queue.begin(), s->compile_queue.end(), j), s->compile_queue.end());
     s->jobs.erase(it);
     return status ? status : 1;
 }
@@ -380,7 +506,9 @@ void fastlec_es_server_destroy(fastlec_es_server* s) {
         s->stop = true;
     }
     s->cv_work.notify_all();
+    s->cv_compile.notify_all();
     if (s->th.joinable()) s->th.join();
+    if (s->compiler.joinable()) s->compiler.join();
     if (s->table.dev) s->dev->release(s->table);
     if (s->files.dev) s->dev->release(s->files);
     delete s;

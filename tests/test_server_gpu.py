@@ -128,3 +128,26 @@ def test_deadline_and_cancel_forced_from_host():
     flag.value = 0
     r = es.fastlec_es_check(c, kernel="interp", cancel_flag=flag, deadline_s=600.0)
     assert r["verdict"] == es.FASTLEC_EQUIVALENT and r["patterns_evaluated"] == 1 << 24
+
+
+def test_server_specialized_tier_switch_mid_job(monkeypatch):
+    """Every job is handed to the compile thread (test hook) and steps are 1 ms, so jobs
+    start on the interpreter and finish on their specialized kernel; each answer must equal
+    the same circuit checked alone on the interpreter, and again when submitted a second
+    time (compiled kernel reused from the first step)."""
+    monkeypatch.setenv("FASTLEC_ES_SERVER_JIT", "2")
+    monkeypatch.setenv("FASTLEC_ES_SERVER_STEP_MS", "1")
+    gs = _jobs(31, 6, 20, 24, 800, 2000, faulty_every=2)
+    circs = [es.fastlec_es_load_aig(g.to_aig()) for g in gs]
+    alone = [_answer(es.fastlec_es_check(c, kernel="interp")) for c in circs]
+    srv = es.Server(8 << 30)
+    try:
+        for rep in range(2):
+            print("submission round", rep, flush=True)
+            tickets = [srv.submit(c) for c in circs]
+            got = [_answer(srv.poll(t, wait=True)) for t in tickets]
+            assert got == alone, rep
+        st = srv.stats()
+        assert st["specialized_slices"] > 0, st
+    finally:
+        srv.close()
