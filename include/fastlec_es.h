@@ -120,10 +120,12 @@ int fastlec_es_info_get(const fastlec_es_circuit *c, fastlec_es_info *info);
  * Section 3.3).  opts may be NULL (defaults).  Blocks until *out is filled. */
 int fastlec_es_check(const fastlec_es_circuit *c, const fastlec_es_options *opts, fastlec_es_result *out);
 
-/* Exact simulation of k circuits of different sizes and input counts in one persistent
- * interpreter launch (whole space each; the option's word range is ignored).  cs: k handles;
- * out: k results.  Returns the first per-circuit error; per-circuit errors also appear as a
- * negative verdict. */
+/* Exact simulation of k circuits of different sizes and input counts (whole space each; the
+ * option's word range is ignored).  Circuits are grouped by value-file size (powers of two of
+ * the row count); each group is one persistent interpreter launch over all its cones, in
+ * longest-processing-time order, with a tuned schedule (or the option's schedule fields) and
+ * recorded once as a hipGraph.  cs: k handles; out: k results.  Returns the first
+ * per-circuit error; per-circuit errors also appear as a negative verdict. */
 int fastlec_es_check_batch(const fastlec_es_circuit *const *cs, size_t k, const fastlec_es_options *opts,
                            fastlec_es_result *out);
 

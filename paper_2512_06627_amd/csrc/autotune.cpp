@@ -149,7 +149,7 @@ void run_batch_graph(Device& dev, const std::vector<Circuit*>& cs, const std::ve
             x->sch.grid == sch.grid && x->sch.lds == sch.lds && x->sch.tile_hw == sch.tile_hw)
             bg = x.get();
     if (!bg) {
-        if (list.size() >= 4) {  // evict the least recently used graph
+        if (list.size() >= 16) {  // evict the least recently used graph (a batch may hold several groups)
             auto it = std::min_element(list.begin(), list.end(),
                                        [](const auto& a, const auto& b) { return a->last_use < b->last_use; });
             BatchGraph* old = it->get();

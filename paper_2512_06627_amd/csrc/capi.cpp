@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <fstream>
 #include <sstream>
 
@@ -213,19 +214,43 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
             v.push_back(const_cast<Circuit*>(&cs[i]->c));
             rs.push_back(range_of(v.back()->plan1.num_inputs, 0, 0));
         }
-        // Schedule: the caller's fields when given, otherwise the autotuner's choice.
-        Schedule sch;
-        if (o.words_per_thread || o.wg_size) sch = default_schedule(dev, v, &o);
-        else sch = autotune(dev, v, rs, stream, o.kernel == FASTLEC_KERNEL_INTERP_HBM);
-        if (o.tile_words) sch.tile_hw = 2ull * o.tile_words;
-        std::vector<uint64_t> best;
-        double ms = 0;
-        run_batch_graph(dev, v, rs, sch, stream, best, &ms);
+        // Groups by value-file size: one launch sizes every wave's file for its largest cone,
+        // so cones with few rows would otherwise run at the occupancy of the largest.  Rows
+        // are bucketed by powers of two; each group gets its own schedule and recorded launch,
+        // and the groups run back to back on the stream.
+        std::map<uint32_t, std::vector<size_t>> groups;
         for (size_t i = 0; i < k; ++i) {
-            std::memset(&out[i], 0, sizeof(out[i]));
-            fill_result(*v[i], rs[i], best[i], &out[i]);
-            out[i].kernel_ms = ms;
+            uint32_t rows = v[i]->plan_for(8).rows, b = 0;
+            while (rows > 1) {
+                rows >>= 1;
+                ++b;
+            }
+            groups[b].push_back(i);
         }
+        double total_ms = 0;
+        for (auto& gi : groups) {
+            std::vector<Circuit*> gv;
+            std::vector<HwRange> gr;
+            for (size_t i : gi.second) {
+                gv.push_back(v[i]);
+                gr.push_back(rs[i]);
+            }
+            // Schedule: the caller's fields when given, otherwise the autotuner's choice.
+            Schedule sch;
+            if (o.words_per_thread || o.wg_size) sch = default_schedule(dev, gv, &o);
+            else sch = autotune(dev, gv, gr, stream, o.kernel == FASTLEC_KERNEL_INTERP_HBM);
+            if (o.tile_words) sch.tile_hw = 2ull * o.tile_words;
+            std::vector<uint64_t> best;
+            double ms = 0;
+            run_batch_graph(dev, gv, gr, sch, stream, best, &ms);
+            total_ms += ms;
+            for (size_t t = 0; t < gi.second.size(); ++t) {
+                const size_t i = gi.second[t];
+                std::memset(&out[i], 0, sizeof(out[i]));
+                fill_result(*v[i], rs[i], best[t], &out[i]);
+            }
+        }
+        for (size_t i = 0; i < k; ++i) out[i].kernel_ms = total_ms;
         return FASTLEC_OK;
     });
 }

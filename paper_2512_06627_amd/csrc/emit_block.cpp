@@ -28,7 +28,7 @@
 namespace fes {
 namespace {
 
-enum class Kind : uint8_t { Vgpr, Sgpr, Operand, Inline };
+enum class Kind : uint8_t { Vgpr, Sgpr, Operand, Inline, Lds };
 
 struct Loc {
     Kind kind = Kind::Operand;
@@ -73,8 +73,9 @@ struct Pool {
         std::sort(free.begin(), free.end(), std::greater<int>());
     }
     // Lowest free register whose bank (number mod 4) is not in `avoid` (bit per bank); a new
-    // register otherwise, skipping at most three numbers (they stay free for later).
-    int take_bank(unsigned avoid) {
+    // register otherwise, skipping at most three numbers (they stay free for later) but never
+    // past `cap`.
+    int take_bank(unsigned avoid, int cap = 1 << 30) {
         if (avoid == 0 || avoid == 15) return take();
         for (size_t i = free.size(); i-- > 0;) {
             const int r = free[i];
@@ -84,7 +85,8 @@ struct Pool {
                 return r;
             }
         }
-        while ((avoid >> (next & 3)) & 1u) give(next++);
+        if (!free.empty()) return take();
+        while (((avoid >> (next & 3)) & 1u) && next + 1 < cap) give(next++);
         return take();
     }
 };
@@ -185,12 +187,75 @@ std::vector<LutStep> schedule(const LutProgram& lp, int dist) {
     return out;
 }
 
-}  // namespace
+// Order for few live vector values, used when the program's order needs more VGPRs than the
+// occupancy target allows: list scheduling that takes the ready step which ends the most
+// live values and starts the fewest (outputs fold their operands away), ties by the
+// program's order.
+std::vector<LutStep> schedule_min_live(const LutProgram& lp) {
+    std::vector<LutStep> in = schedule(lp, 1);
+    const size_t N = in.size();
+    auto nleaves = [](const LutStep& st) -> uint32_t { return st.op == LutStep::ScalarAnd ? 2 : st.nleaves; };
+    auto is_vec = [](const LutRef& r) { return r.kind == LutRef::Varying; };
+    std::map<uint64_t, size_t> producer;
+    std::map<uint64_t, uint32_t> remaining;  // unscheduled readers of a vector value
+    for (size_t i = 0; i < N; ++i) {
+        if (in[i].op == LutStep::Lut) producer[((uint64_t)LutRef::Varying << 32) | in[i].dst] = i;
+        if (in[i].op == LutStep::ScalarAnd) producer[((uint64_t)LutRef::Uniform << 32) | in[i].dst] = i;
+    }
+    std::vector<std::vector<size_t>> succs(N);
+    std::vector<size_t> waiting(N, 0);
+    for (size_t i = 0; i < N; ++i) {
+        std::vector<size_t> ps;
+        for (uint32_t j = 0; j < nleaves(in[i]); ++j) {
+            const uint64_t key = ((uint64_t)in[i].leaf[j].kind << 32) | in[i].leaf[j].index;
+            if (is_vec(in[i].leaf[j])) ++remaining[key];
+            auto it = producer.find(key);
+            if (it != producer.end() && std::find(ps.begin(), ps.end(), it->second) == ps.end()) ps.push_back(it->second);
+        }
+        waiting[i] = ps.size();
+        for (size_t p : ps) succs[p].push_back(i);
+    }
+    std::set<size_t> ready;
+    for (size_t i = 0; i < N; ++i)
+        if (!waiting[i]) ready.insert(i);
+    std::vector<LutStep> out;
+    out.reserve(N);
+    while (!ready.empty()) {
+        size_t pick = N;
+        int best = 1 << 30;
+        for (size_t i : ready) {
+            const LutStep& st = in[i];
+            int delta = 0;
+            if (st.op == LutStep::Lut && remaining.count(((uint64_t)LutRef::Varying << 32) | st.dst)) delta += 1;
+            std::vector<uint64_t> seen;
+            for (uint32_t j = 0; j < nleaves(st); ++j) {
+                if (!is_vec(st.leaf[j])) continue;
+                const uint64_t key = ((uint64_t)st.leaf[j].kind << 32) | st.leaf[j].index;
+                if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
+                seen.push_back(key);
+                if (remaining[key] == 1) delta -= 1;
+            }
+            if (delta < best) {
+                best = delta;
+                pick = i;
+                if (delta < 0) break;  // frees a value: take the earliest such step
+            }
+        }
+        ready.erase(pick);
+        const LutStep& st = in[pick];
+        for (uint32_t j = 0; j < nleaves(st); ++j)
+            if (is_vec(st.leaf[j])) --remaining[((uint64_t)st.leaf[j].kind << 32) | st.leaf[j].index];
+        out.push_back(st);
+        for (size_t q : succs[pick])
+            if (--waiting[q] == 0) ready.insert(q);
+    }
+    return out;
+}
 
-bool emit_block_body(const LutProgram& lp, int vgpr_limit, int sgpr_limit, int sgpr_base, int word_operand_limit,
-                     int dist, bool bank_aware, std::string* code, BlockStats* stats) {
+bool emit_with_order(const LutProgram& lp, const std::vector<LutStep>& steps, int vgpr_limit, int sgpr_limit,
+                     int sgpr_base, int word_operand_limit, bool bank_aware, int lds_slots, std::string* code,
+                     BlockStats* stats) {
     const uint32_t n = lp.num_inputs;
-    const std::vector<LutStep> steps = schedule(lp, dist);
     // ---- asm operand numbering ------------------------------------------------------------
     // %0 m (output), %1 low and %2 high word of the base half-word index, then the lane
     // inputs 5..min(n,11)-1, then plan-time words (VGPR operands) up to the limit.
@@ -230,6 +295,13 @@ bool emit_block_body(const LutProgram& lp, int vgpr_limit, int sgpr_limit, int s
         word_operand[u.second] = 1 + (int)in_cons.size();
         in_cons.push_back("\"v\"(w" + std::to_string(u.second) + ")");
     }
+    // LDS spill slots: the lane's byte address in the wave's spill area; slot s is at offset
+    // 256*s (64 lanes x 4 bytes).
+    int spill_operand = -1;
+    if (lds_slots > 0) {
+        spill_operand = 1 + (int)in_cons.size();
+        in_cons.push_back("\"v\"(spill_addr)");
+    }
 
     // ---- uses of every value ------------------------------------------------------------
     std::map<uint64_t, size_t> last;
@@ -255,9 +327,50 @@ bool emit_block_body(const LutProgram& lp, int vgpr_limit, int sgpr_limit, int s
     std::map<uint64_t, int> vcopy;  // VGPR copy of a wave-uniform value held in an SGPR
     std::ostringstream a;  // asm text, one instruction per line
     uint32_t n_valu = 0, n_salu = 0, n_copies = 0;
-    auto line = [&](const std::string& s) { a << s << "\\n\\t"; };
+    // One string literal per instruction (adjacent literals concatenate): clang analyses a
+    // single literal with operand references in time quadratic in its length.
+    auto line = [&](const std::string& s) { a << "        \"" << s << "\\n\\t\"\n"; };
     line("v_mov_b32 %0, 0");
     ++n_valu;
+    // A new VGPR at step t.  When all vgpr_limit registers are taken and LDS slots are
+    // available, the vector value whose next reader is farthest away goes to an LDS slot
+    // (ds_write_b32) and is read back (ds_read_b32, then a wait) right before that reader.
+    // Values read at step t stay in registers.  LDS operations of a wave execute in order, so
+    // a read-back always sees its own write.
+    Pool lp_slots;
+    bool vgpr_failed = false;
+    uint32_t n_lds = 0;
+    auto take_v = [&](size_t t, unsigned avoid) -> int {
+        if (!vp.free.empty() || vp.next < vgpr_limit || lds_slots <= 0) return vp.take_bank(avoid, vgpr_limit);
+        uint64_t victim = 0;
+        size_t far = 0;
+        bool found = false;
+        for (auto& kv : where) {
+            if (kv.second.kind != Kind::Vgpr) continue;
+            const std::vector<size_t>& u = uses[kv.first];
+            auto nx = std::lower_bound(u.begin(), u.end(), t);
+            if (nx != u.end() && *nx == t) continue;  // read at this step
+            const size_t next = nx == u.end() ? SIZE_MAX : *nx;
+            if (!found || next > far) {
+                found = true;
+                far = next;
+                victim = kv.first;
+            }
+        }
+        if (!found || (lp_slots.free.empty() && lp_slots.next >= lds_slots)) {
+            vgpr_failed = true;
+            return vp.take_bank(avoid);
+        }
+        Loc& l = where[victim];
+        const int reg = l.reg;
+        const int slot = lp_slots.take();
+        char b[80];
+        std::snprintf(b, sizeof b, "ds_write_b32 %%%d, v%d offset:%d", spill_operand, reg, 256 * slot);
+        line(b);
+        ++n_lds;
+        l = Loc{Kind::Lds, slot, 0};
+        return reg;
+    };
     // A new SGPR at step t.  When the pool is full, the wave-uniform value with only VALU
     // readers left whose next reader is farthest moves to a VGPR (v_mov_b32 v, s); values
     // read at step t stay.  Values never move back: no VALU instruction writes an SGPR.
@@ -287,7 +400,7 @@ bool emit_block_body(const LutProgram& lp, int vgpr_limit, int sgpr_limit, int s
         }
         Loc& l = where[victim];
         const int sreg = l.reg;
-        const int vreg = vp.take();
+        const int vreg = take_v(t, 0);
         char b[64];
         std::snprintf(b, sizeof b, "v_mov_b32 v%d, s%d", vreg, sreg);
         line(b);
@@ -319,7 +432,7 @@ bool emit_block_body(const LutProgram& lp, int vgpr_limit, int sgpr_limit, int s
                 auto w = where.find(key_of(r));
                 if (w != where.end()) return w->second;
                 l.kind = Kind::Vgpr;
-                l.reg = vp.take();
+                l.reg = take_v(t, 0);
                 char buf[64];
                 std::snprintf(buf, sizeof buf, "v_mov_b32 v%d, 0x%08x", l.reg, lp.words[r.index]);
                 line(buf);
@@ -342,7 +455,21 @@ bool emit_block_body(const LutProgram& lp, int vgpr_limit, int sgpr_limit, int s
                 where[key_of(r)] = l;
                 return l;
             }
-            default: return where.at(key_of(r));
+            default: {
+                Loc& w = where.at(key_of(r));
+                if (w.kind != Kind::Lds) return w;
+                const int slot = w.reg;
+                const int reg = take_v(t, 0);
+                char buf[96];
+                std::snprintf(buf, sizeof buf, "ds_read_b32 v%d, %%%d offset:%d", reg, spill_operand, 256 * slot);
+                line(buf);
+                line("s_waitcnt lgkmcnt(0)");
+                ++n_lds;
+                lp_slots.give(slot);
+                Loc& w2 = where.at(key_of(r));  // take_v may have rehashed nothing, but re-find
+                w2 = Loc{Kind::Vgpr, reg, 0};
+                return w2;
+            }
         }
     };
     auto release = [&](const LutRef& r, size_t t) {
@@ -352,6 +479,7 @@ bool emit_block_body(const LutProgram& lp, int vgpr_limit, int sgpr_limit, int s
         if (lu != last.end() && lu->second > t) return;
         if (it->second.kind == Kind::Vgpr) vp.give(it->second.reg);
         if (it->second.kind == Kind::Sgpr) sp.give(it->second.reg - sgpr_base);
+        if (it->second.kind == Kind::Lds) lp_slots.give(it->second.reg);
         where.erase(it);
         auto vc = vcopy.find(key_of(r));
         if (vc != vcopy.end()) {
@@ -400,7 +528,7 @@ bool emit_block_body(const LutProgram& lp, int vgpr_limit, int sgpr_limit, int s
                 sg = src[j].reg;
                 continue;
             }
-            const int tv = vp.take();
+            const int tv = take_v(t, 0);
             std::snprintf(buf, sizeof buf, "v_mov_b32 v%d, s%d", tv, src[j].reg);
             line(buf);
             ++n_valu;
@@ -430,7 +558,7 @@ bool emit_block_body(const LutProgram& lp, int vgpr_limit, int sgpr_limit, int s
                     }
                 }
             }
-            Loc d{Kind::Vgpr, vp.take_bank(avoid), 0};
+            Loc d{Kind::Vgpr, take_v(t, avoid), 0};
             const std::string s0 = loc_text(src[0]);
             const std::string s1 = loc_text(src[k >= 2 ? 1 : 0]);
             const std::string s2 = loc_text(src[k >= 3 ? 2 : (k >= 2 ? 1 : 0)]);
@@ -456,6 +584,7 @@ bool emit_block_body(const LutProgram& lp, int vgpr_limit, int sgpr_limit, int s
             ++n_valu;
         }
     }
+    if (n_lds) line("s_waitcnt lgkmcnt(0)");  // no spill write outlives the block
     const int nv = vp.high, ns = sp.high;
     if (stats) {
         stats->vgprs = nv;
@@ -465,12 +594,14 @@ bool emit_block_body(const LutProgram& lp, int vgpr_limit, int sgpr_limit, int s
         stats->copies = n_copies;
         stats->word_operands = (int)word_operand.size();
         stats->spills = n_spills;
+        stats->lds_ops = n_lds;
+        stats->lds_slots = lp_slots.high;
     }
-    if (spill_failed || nv > vgpr_limit || ns > sgpr_limit) return false;
+    if (spill_failed || vgpr_failed || nv > vgpr_limit || ns > sgpr_limit) return false;
     // ---- the asm statement -------------------------------------------------------------
     std::ostringstream o;
     o << "      u32 m0;\n"
-         "      asm volatile(\"" << a.str() << "\"\n        : \"=&v\"(m0)\n        : ";
+         "      asm volatile(\n" << a.str() << "        : \"=&v\"(m0)\n        : ";
     for (size_t i = 0; i < in_cons.size(); ++i) o << (i ? ", " : "") << in_cons[i];
     o << "\n        : \"scc\"";
     for (int r = 0; r < nv; ++r) o << ", \"v" << r << "\"";
@@ -478,6 +609,25 @@ bool emit_block_body(const LutProgram& lp, int vgpr_limit, int sgpr_limit, int s
     o << ");\n";
     *code = o.str();
     return true;
+}
+
+}  // namespace
+
+bool emit_block_body(const LutProgram& lp, int vgpr_limit, int sgpr_limit, int sgpr_base, int word_operand_limit,
+                     int dist, bool bank_aware, int lds_slots, std::string* code, BlockStats* stats) {
+    if (emit_with_order(lp, schedule(lp, dist), vgpr_limit, sgpr_limit, sgpr_base, word_operand_limit, bank_aware,
+                        lds_slots, code, stats))
+        return true;
+    BlockStats first = stats ? *stats : BlockStats{};
+    if (emit_with_order(lp, schedule_min_live(lp), vgpr_limit, sgpr_limit, sgpr_base, word_operand_limit,
+                        bank_aware, lds_slots, code, stats)) {
+        if (stats) stats->min_live_order = true;
+        return true;
+    }
+    const int min_live_vgprs = stats ? stats->vgprs : 0;
+    if (stats && first.vgprs < stats->vgprs) *stats = first;
+    if (stats) stats->vgprs_min_live = min_live_vgprs;
+    return false;
 }
 
 }  // namespace fes

@@ -55,9 +55,38 @@ int jit_passes(const LutProgram& lp) {
     return lp.num_inputs >= 12 ? want : 1;
 }
 
-std::string jit_source(const LutProgram& lp, int waves_per_eu, int block) {
+std::string jit_source(const LutProgram& lp, int waves_per_eu, int block, int* waves_used) {
     std::ostringstream o;
     const uint32_t n = lp.num_inputs;
+    // One asm block per pass when it fits: at the requested occupancy, else at two waves per
+    // SIMD (a wide cone's live values need up to 256 VGPRs); otherwise one asm statement per
+    // gate with the compiler's register allocation.  The compiler keeps its own values
+    // (claims, bounds, pointers, lane masks, words, the ballot) in the registers the block
+    // leaves alone: about 24 VGPRs and 30 SGPRs.
+    std::string block_body;
+    BlockStats bs;
+    int waves = waves_per_eu;
+    int lds_slots = 0;
+    if (jit_passes(lp) == 1 && specialized_emit_mode() == 1) {
+        // Attempts: (waves, LDS spill slots per wave).  LDS holds 160 KB per CU, shared by
+        // 4 x waves waves; a slot is 256 bytes; ds offsets reach 255 slots.
+        std::vector<std::pair<int, int>> tries = {{waves_per_eu, 0}};
+        if (waves_per_eu > 2) tries.push_back({2, 0});
+        for (int w : {std::min(waves_per_eu, 2), 1}) tries.push_back({w, std::min(255, 163840 / (4 * w) / 256)});
+        const int cap = specialized_vgpr_cap();
+        for (auto& tr : tries) {
+            int vgpr_budget = std::min(256, 512 / tr.first / 8 * 8) - 24;
+            if (cap > 0) vgpr_budget = std::min(vgpr_budget, cap);
+            if (emit_block_body(lp, vgpr_budget, 64, 0, 20, specialized_latency_slots(), specialized_bank_aware() != 0,
+                                tr.second, &block_body, &bs)) {
+                waves = tr.first;
+                lds_slots = bs.lds_slots;
+                break;
+            }
+            block_body.clear();
+        }
+    }
+    if (waves_used) *waves_used = waves;
     // P passes (64 half-words each) per loop iteration.  With P = 2 every wave-uniform value
     // holds both passes in one 64-bit scalar register pair (pass 0 in the low half), so one
     // scalar instruction serves two passes; the LUT steps are emitted once per pass.
@@ -68,7 +97,7 @@ std::string jit_source(const LutProgram& lp, int waves_per_eu, int block) {
       << P << " passes per iteration\n";
     o << "typedef unsigned int u32;\ntypedef unsigned long long u64;\n";
     o << "extern \"C\" __global__ void __launch_bounds__(" << block << ") __attribute__((amdgpu_waves_per_eu("
-      << waves_per_eu << ", " << waves_per_eu << ")))\n";
+      << waves << ", " << waves << ")))\n";
     o << "fes_es_kernel(u64 hw_begin, u64 hw_end, u64 hw_first, u64 tile_hw, u64 total_items,\n"
          "              u64* __restrict__ next_item, u64* __restrict__ best, const int* __restrict__ cancel) {\n";
     o << "  const u32 lane = threadIdx.x & 63u;\n";
@@ -82,6 +111,11 @@ std::string jit_source(const LutProgram& lp, int waves_per_eu, int block) {
             std::snprintf(buf, sizeof buf, "  const u64 ww%u = 0x%08X%08Xull;\n", i, lp.words[i], lp.words[i]);
             o << buf;
         }
+    }
+    if (lds_slots) {  // per-wave spill area of the asm block: slot s of lane l at [s * 64 + l]
+        o << "  __shared__ u32 fes_spill[" << (block / 64) * lds_slots * 64 << "];\n"
+          << "  const u32 spill_addr = (u32)(unsigned long)(__attribute__((address_space(3))) u32*)(fes_spill + (threadIdx.x >> 6) * "
+          << lds_slots * 64 << "u + lane);\n";
     }
     // Control flow stays wave-uniform: every lane takes part in the claim (lane 0 adds 1, the
     // others 0) and in the atomicMin (all lanes hold the same value), so no branch depends on
@@ -101,21 +135,16 @@ std::string jit_source(const LutProgram& lp, int waves_per_eu, int block) {
          "      if (32ull * base >= best_seen) break;\n"
          "      // read for the next pass: the load completes while this pass runs\n"
          "      const u64 b_next = __hip_atomic_load(best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);\n";
-    std::string block_body;
     if (P == 1 && specialized_emit_mode() == 1) {
-        // The compiler keeps its own values (claims, bounds, pointers, lane masks, words, the
-        // ballot) in the registers that the block leaves alone: about 24 VGPRs and 30 SGPRs.
-        const int vgpr_budget = std::min(256, 512 / waves_per_eu / 8 * 8) - 24;
-        BlockStats bs;
-        if (!emit_block_body(lp, vgpr_budget, 64, 0, 20, specialized_latency_slots(), specialized_bank_aware() != 0,
-                             &block_body, &bs)) {
-            block_body.clear();
-            o << "      // one asm block would need " << bs.vgprs << " VGPRs and " << bs.sgprs << " SGPRs\n";
-        }
-        if (!block_body.empty())
+        if (block_body.empty())
+            o << "      // one asm block would need " << bs.vgprs << " VGPRs (" << bs.vgprs_min_live
+              << " in the pressure-aware order) and " << bs.sgprs << " SGPRs\n";
+        else
             o << "      // one asm block: " << bs.vgprs << " VGPRs, " << bs.sgprs << " SGPRs, " << bs.valu
               << " VALU and " << bs.salu << " SALU instructions, " << bs.copies << " scalar-operand copies, " << bs.spills
-              << " values moved to VGPRs\n";
+              << " values moved to VGPRs, " << waves << " waves per SIMD"
+              << (lds_slots ? ", " + std::to_string(bs.lds_ops) + " LDS spill operations in " + std::to_string(lds_slots) + " slots" : std::string())
+              << "\n";
     }
     if (!block_body.empty()) {
         o << "      const u32 base_lo = (u32)base, base_hi = (u32)(base >> 32);\n" << block_body;
@@ -305,6 +334,7 @@ int env_int(const char* name, int dflt, int lo, int hi) {
 }  // namespace
 
 int specialized_latency_slots() { return env_int("FASTLEC_ES_JIT_DIST", 1, 1, 64); }
+int specialized_vgpr_cap() { return env_int("FASTLEC_ES_JIT_VGPR_CAP", 0, 0, 256); }
 int specialized_bank_aware() { return env_int("FASTLEC_ES_JIT_BANKS", 1, 0, 1); }
 int specialized_emit_mode() { return env_int("FASTLEC_ES_JIT_EMIT", 1, 0, 1); }
 int specialized_waves_per_eu() { return env_int("FASTLEC_ES_JIT_WAVES", 3, 1, 8); }
@@ -328,7 +358,7 @@ std::shared_ptr<JitKernel> jit_kernel(Circuit& c, int waves_per_eu, double* comp
     }
     std::lock_guard<std::mutex> g(k->mu);
     if (!k->code.empty()) return k;
-    k->source = jit_source(c.lut_program(), waves_per_eu, k->block);
+    k->source = jit_source(c.lut_program(), waves_per_eu, k->block, &k->waves_used);
     k->passes = jit_passes(c.lut_program());
     k->hash = fnv1a(k->source);
     {
@@ -371,7 +401,7 @@ JitLaunchPlan jit_prepare(Device& dev, JitKernel& k, const HwRange& r, uint64_t 
             // threads puts block/256 waves on each of the CU's four SIMDs), never more: the
             // register count decides whether one more wave would fit, and at four waves per
             // SIMD the 16x16 kernel runs a third slower than at three.
-            const int target = std::max(1, k.waves_per_eu * 4 * 64 / k.block);
+            const int target = std::max(1, k.waves_used * 4 * 64 / k.block);
             k.per_device[dev.ordinal] = {mod, fn};
             k.blocks_per_cu[dev.ordinal] = std::max(1, std::min(b, target));
         }

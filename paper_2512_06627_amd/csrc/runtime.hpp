@@ -35,7 +35,8 @@ struct JitKernel {
     std::string source;
     std::vector<char> code;  // code object
     uint64_t hash = 0;
-    int waves_per_eu = 2;
+    int waves_per_eu = 2;  // requested occupancy (the cache key)
+    int waves_used = 2;    // occupancy the source was built for (the launch grid follows it)
     int block = 256;
     int passes = 1;  // 64-half-word passes per loop iteration; tiles are multiples of this
     double compile_ms = 0;
@@ -145,19 +146,27 @@ struct JitLaunchPlan {
 };
 JitLaunchPlan jit_prepare(Device& dev, JitKernel& k, const HwRange& r, uint64_t tile_hw);
 void jit_enqueue(const JitLaunchPlan& lp, uint64_t* next_item, uint64_t* best, const int* cancel, hipStream_t stream);
-std::string jit_source(const LutProgram& lp, int waves_per_eu, int block);
+std::string jit_source(const LutProgram& lp, int waves_per_eu, int block, int* waves_used = nullptr);
 
 // The per-pass body as one asm statement with planner-assigned registers (v0.., s<sgpr_base>..).
 // Returns false, with the register counts in stats, when it needs more than the limits.
 struct BlockStats {
     int vgprs = 0, sgprs = 0, word_operands = 0;
     uint32_t valu = 0, salu = 0, copies = 0, spills = 0;
+    bool min_live_order = false;  // the program order did not fit; a pressure-aware order did
+    int vgprs_min_live = 0;       // VGPRs of the pressure-aware order when neither fits
+    uint32_t lds_ops = 0;         // spill writes and read-backs
+    int lds_slots = 0;            // LDS slots used per wave
 };
 // dist: slots between a VALU result and its first reader that the scheduler aims for.
 // bank_aware: place a LUT result in a VGPR bank other than its first reader's other operands.
+// lds_slots > 0: vector values beyond vgpr_limit may live in that many per-wave LDS slots
+// (256 bytes each); the block then reads the asm operand spill_addr (the lane's byte address
+// of slot 0 in the wave's area).
 bool emit_block_body(const LutProgram& lp, int vgpr_limit, int sgpr_limit, int sgpr_base, int word_operand_limit,
-                     int dist, bool bank_aware, std::string* code, BlockStats* stats);
+                     int dist, bool bank_aware, int lds_slots, std::string* code, BlockStats* stats);
 int specialized_bank_aware();     // FASTLEC_ES_JIT_BANKS
+int specialized_vgpr_cap();       // FASTLEC_ES_JIT_VGPR_CAP: lower VGPR limit of the asm block (tests)
 int specialized_latency_slots();  // FASTLEC_ES_JIT_DIST
 int specialized_emit_mode();  // FASTLEC_ES_JIT_EMIT: 1 one asm block per pass, 0 one asm statement per gate
 int jit_passes(const LutProgram& lp);

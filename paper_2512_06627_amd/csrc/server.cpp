@@ -129,8 +129,18 @@ void fastlec_es_server::compile_loop() {
             std::unique_lock<std::mutex> g(mu);
             cv_compile.wait(g, [&] { return stop || !compile_queue.empty(); });
             if (stop) return;
-            j = compile_queue.front();
-            compile_queue.pop_front();
+            // Largest remaining work first: it gains the most from the specialized kernel.
+            auto pick = compile_queue.begin();
+            double most = -1;
+            for (auto it = compile_queue.begin(); it != compile_queue.end(); ++it) {
+                const double w = (double)(*it)->c->plan1.num_gate_instrs * (double)((*it)->range.end - (*it)->cursor);
+                if (!(*it)->done && w > most) {
+                    most = w;
+                    pick = it;
+                }
+            }
+            j = *pick;
+            compile_queue.erase(pick);
             if (j->done) continue;
             j->compiling = true;
         }
@@ -156,12 +166,12 @@ void fastlec_es_server::plan_tiers(const std::vector<Job*>& act) {
             j->jit = k;
             continue;
         }
-        // Remaining interpreter time vs compile time (hipRTC takes about 0.2 ms per AND
+        // Remaining interpreter time vs compile time (hipRTC: about 0.2 s plus 0.03 ms per AND
         // gate for these kernels; compiles run one at a time).
         const double gates = std::max<uint32_t>(1, j->c->plan1.num_gate_instrs);
         const double interp_s = 32.0 * gates * (double)(j->range.end - j->cursor) / rate;
-        const double compile_s = 0.3 + 2.5e-4 * gates;
-        if (jit_mode == 2 || interp_s > 2.0 * compile_s + 1.0) {
+        const double compile_s = 0.2 + 3e-5 * gates;
+        if (jit_mode == 2 || interp_s > 2.0 * compile_s + 0.5) {
             j->compile_queued = true;
             compile_queue.push_back(j);
             cv_compile.notify_one();

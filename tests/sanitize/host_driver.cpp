@@ -44,11 +44,12 @@ int main(int argc, char** argv) {
         for (int policy : {0, 2}) {
             const LutProgram lp = make_lut_program(g, p1, policy);
             for (int dist : {1, 6})
-                for (bool banks : {false, true}) {
-                    std::string code;
-                    BlockStats st;
-                    emit_block_body(lp, 232, 64, 0, 20, dist, banks, &code, &st);
-                }
+                for (bool banks : {false, true})
+                    for (int cap : {232, 24}) {  // 24 VGPRs: spills to LDS
+                        std::string code;
+                        BlockStats st;
+                        emit_block_body(lp, cap, 64, 0, 20, dist, banks, cap < 64 ? 255 : 0, &code, &st);
+                    }
             for (size_t i = 0; i < hws.size(); ++i) {
                 const uint64_t h = g.num_inputs >= 5 ? hws[i] % (1ull << (g.num_inputs - 5)) : 0;
                 const uint32_t w = eval_lut_program(lp, h);

@@ -2,8 +2,9 @@
 
 The block's text is exactly what runs on the GPU once the compiler has substituted its
 operands (%0 the miter word, %1/%2 the base index, then lane masks and words).  A
-per-lane model of the six instructions it may contain (v_bitop3_b32, v_mov_b32,
-s_and_b32, s_andn2_b32, s_nor_b32, s_bfe_i32) runs it for whole passes, and every lane's
+per-lane model of the instructions it may contain (v_bitop3_b32, v_mov_b32,
+s_and_b32, s_andn2_b32, s_nor_b32, s_bfe_i32, and the LDS spill pair ds_write_b32 /
+ds_read_b32 with s_waitcnt) runs it for whole passes, and every lane's
 miter word must equal the oracle's.  A register-allocation mistake (a value overwritten
 while still live, a wrong operand, a lost complement) changes some lane's word.
 """
@@ -19,26 +20,34 @@ import paper_2512_06627_amd as es
 M32 = np.uint64(0xFFFFFFFF)
 
 
-@pytest.fixture(autouse=True, params=[("0", "6", "0"), ("2", "1", "0"), ("2", "6", "1")],
-                ids=["scalar-unit", "all-valu", "all-valu-spaced-banks"])
+@pytest.fixture(autouse=True, params=[("0", "6", "0", "0"), ("2", "1", "0", "0"), ("2", "6", "1", "0"),
+                                      ("2", "1", "1", "24")],
+                ids=["scalar-unit", "all-valu", "all-valu-spaced-banks", "all-valu-lds-spills"])
 def block_emitter(monkeypatch, request):
     """Mappings and emitter options: wave-uniform gates on the scalar unit (policy 0) or all
-    gates in VALU LUTs (policy 2); latency spacing; bank-aware VGPR choice."""
-    policy, dist, banks = request.param
+    gates in VALU LUTs (policy 2); latency spacing; bank-aware VGPR choice; a 24-VGPR cap
+    that forces values into LDS spill slots."""
+    policy, dist, banks, cap = request.param
     monkeypatch.setenv("FASTLEC_ES_JIT_EMIT", "1")
     monkeypatch.setenv("FASTLEC_ES_JIT_SCALAR", policy)
     monkeypatch.setenv("FASTLEC_ES_JIT_DIST", dist)
     monkeypatch.setenv("FASTLEC_ES_JIT_BANKS", banks)
+    monkeypatch.setenv("FASTLEC_ES_JIT_VGPR_CAP", cap)
 
 
 def parse_block(src):
-    start = src.index('asm volatile("') + len('asm volatile("')
-    end = src.index('"\n        : "=&v"(m0)')
-    text = src[start:end].split("\\n\\t")
-    cons = src[end:].split("\n")[2]
+    """Instruction lines (one string literal each), input operands and word values."""
+    start = src.index("asm volatile(\n") + len("asm volatile(\n")
+    end = src.index('        : "=&v"(m0)')
+    lines = []
+    for t in src[start:end].splitlines():
+        t = t.strip()
+        assert t.startswith('"') and t.endswith('\\n\\t"'), t
+        lines.append(t[1:-5])
+    cons = src[end:].split("\n")[1]
     inputs = re.findall(r'"([sv])"\((\w+)\)', cons)
     words = {m.group(1): int(m.group(2), 16) for m in re.finditer(r"const u32 (w\d+) = 0x([0-9A-F]+)u;", src)}
-    return [t for t in text if t.strip()], inputs, words
+    return lines, inputs, words
 
 
 def run_block(lines, inputs, words, base):
@@ -52,9 +61,11 @@ def run_block(lines, inputs, words, base):
         elif name.startswith("x"):
             i = int(name[1:])
             ops[k + 1] = (np.uint64(0) - ((lane >> np.uint64(i - 5)) & np.uint64(1))) & M32
+        elif name == "spill_addr":
+            ops[k + 1] = np.uint64(0x4000) + lane * np.uint64(4)  # any wave base; lane-strided
         else:
             ops[k + 1] = np.uint64(words[name])
-    v, s = {}, {}
+    v, s, lds = {}, {}, {}
 
     def val(tok):
         tok = tok.strip()
@@ -86,6 +97,22 @@ def run_block(lines, inputs, words, base):
             rest, t = rest.split(" bitop3:")
             table = int(t, 0)
         a = [x.strip() for x in rest.split(",")]
+        if op == "ds_write_b32":  # addr, data offset:N
+            addr, rest2 = a[0], a[1].split()
+            off = int(rest2[1].split(":")[1]) if len(rest2) > 1 else 0
+            base = val(addr)
+            data = np.broadcast_to(val(rest2[0]), (64,))
+            for l in range(64):
+                lds[int(base[l]) + off] = int(data[l])
+            continue
+        if op == "ds_read_b32":  # dst, addr offset:N
+            dst, rest2 = a[0], a[1].split()
+            off = int(rest2[1].split(":")[1]) if len(rest2) > 1 else 0
+            base = val(rest2[0])
+            put(dst, np.array([lds[int(base[l]) + off] for l in range(64)], dtype=np.uint64), False)
+            continue
+        if op == "s_waitcnt":
+            continue
         if op == "v_bitop3_b32":
             assert sum(1 for x in a[1:] if x[0] == "s") <= 1 or len({x for x in a[1:] if x[0] == "s"}) == 1
             x, y, z = (np.broadcast_to(val(t), (64,)) for t in a[1:])

@@ -252,3 +252,62 @@ def test_cached_schedule_refits_larger_batch(monkeypatch):
         print("batch of one cone, rows", rows, flush=True)
         res = es.fastlec_es_check_batch([c])
         assert (res[0]["cex"] if res[0]["verdict"] else None) == oracle.check(g.to_aag(), threads=8), rows
+
+
+@pytest.mark.parametrize("n", [40, 52, 63])
+def test_high_input_bits_in_word_ranges(n):
+    """Inputs above bit 36 of the pattern index come from the high word of the base index.
+    Minterm miters whose failing patterns have high bits set are checked on word windows
+    around the targets: a window holding a target reports it (the lower one first), a window
+    just below it is equivalent with exactly its patterns simulated."""
+    rng = miters.SplitMix64(n)
+    hi = rng.below(1 << (n - 1)) | (1 << (n - 1))      # top input set
+    lo = hi - 64 * rng.between(3, 200) - rng.below(64)  # a second target a few words lower
+    g = miters.minterm_miter(n, [hi, lo])
+    c = es.fastlec_es_load_aig(g.to_aig())
+    for kernel in KERNELS:
+        w_lo, w_hi = lo // 64, hi // 64
+        r = es.fastlec_es_check(c, kernel=kernel, begin_word=w_lo - 5, end_word=w_hi + 7)
+        assert r["verdict"] == es.FASTLEC_NONEQUIVALENT and r["cex"] == lo, (kernel, r)
+        r = es.fastlec_es_check(c, kernel=kernel, begin_word=w_lo + 1, end_word=w_hi + 1)
+        assert r["verdict"] == es.FASTLEC_NONEQUIVALENT and r["cex"] == hi, (kernel, r)
+        r = es.fastlec_es_check(c, kernel=kernel, begin_word=w_hi - 300, end_word=w_hi)
+        if w_lo < w_hi - 300:
+            assert r["verdict"] == es.FASTLEC_EQUIVALENT and r["patterns_evaluated"] == 64 * 300, (kernel, r)
+    # the oracle agrees on the same windows (it scans patterns directly)
+    o = oracle.Circuit(g.to_aag())
+    assert o.lowest_failure(64 * (lo // 64 - 5), 64 * (hi // 64 + 7), threads=4)[0] == lo
+
+
+def test_specialized_lds_spills_match_oracle(monkeypatch):
+    """The asm block capped at 24 VGPRs keeps most values in LDS spill slots (ds_write_b32 /
+    ds_read_b32); answers on the stored workloads and on layered cones must not change."""
+    monkeypatch.setenv("FASTLEC_ES_JIT_VGPR_CAP", "24")
+    for name in ("mult12_array_booth_f1", "mult12_array_booth_f3", "mac8_fused_separate_f1", "mult16_array_booth_f2"):
+        c = es.fastlec_es_load_aig(miters.workload(name).to_aig())
+        src = es.fastlec_es_specialized_source(c, 3)
+        assert "LDS spill operations" in src, name
+        print("spilled kernel", name, flush=True)
+        assert gpu_answer(c, kernel="specialized") == expected(name), name
+    rng = miters.SplitMix64(88)
+    for i in range(4):
+        g = miters.layered_cone_miter(8800 + i, rng.between(12, 18), rng.between(800, 3000),
+                                      fault_seed=(i + 1 if i % 2 else None))
+        c = es.fastlec_es_load_aig(g.to_aig())
+        assert gpu_answer(c, kernel="specialized") == oracle.check(g.to_aag(), threads=8), i
+
+
+def test_wide_cones_specialized_vs_interpreter():
+    """Cones whose live values exceed the three-wave register budget run at two or one wave per
+    SIMD with LDS spills; their answers must equal the interpreter's (checked against the
+    oracle elsewhere) on the whole space."""
+    for size, n in ((12000, 22), (20000, 22)):
+        for fault in (None, 5):
+            g = miters.layered_cone_miter(900000 + size, n, size, fault_seed=fault)
+            c = es.fastlec_es_load_aig(g.to_aig())
+            src = es.fastlec_es_specialized_source(c, 3)
+            assert "one asm block:" in src and ("2 waves per SIMD" in src or "1 waves per SIMD" in src), size
+            if size == 20000:
+                assert "LDS spill" in src
+            print("wide cone", size, n, fault, flush=True)
+            assert gpu_answer(c, kernel="specialized") == gpu_answer(c, kernel="interp"), (size, fault)
