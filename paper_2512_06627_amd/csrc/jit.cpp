@@ -49,12 +49,6 @@ bool is_scalar(const LutRef& r) {
 
 }  // namespace
 
-int jit_passes(const LutProgram& lp) {
-    const char* v = std::getenv("FASTLEC_ES_JIT_PASSES");
-    const int want = (v && *v == '2') ? 2 : 1;
-    return lp.num_inputs >= 12 ? want : 1;
-}
-
 std::string jit_source(const LutProgram& lp, int waves_per_eu, int block, int* waves_used) {
     std::ostringstream o;
     const uint32_t n = lp.num_inputs;
@@ -67,7 +61,7 @@ std::string jit_source(const LutProgram& lp, int waves_per_eu, int block, int* w
     BlockStats bs;
     int waves = waves_per_eu;
     int lds_slots = 0;
-    if (jit_passes(lp) == 1 && specialized_emit_mode() == 1) {
+    if (specialized_emit_mode() == 1) {
         // Attempts: (waves, LDS spill slots per wave).  LDS holds 160 KB per CU, shared by
         // 4 x waves waves; a slot is 256 bytes; ds offsets reach 255 slots.
         std::vector<std::pair<int, int>> tries = {{waves_per_eu, 0}};
@@ -87,14 +81,10 @@ std::string jit_source(const LutProgram& lp, int waves_per_eu, int block, int* w
         }
     }
     if (waves_used) *waves_used = waves;
-    // P passes (64 half-words each) per loop iteration.  With P = 2 every wave-uniform value
-    // holds both passes in one 64-bit scalar register pair (pass 0 in the low half), so one
-    // scalar instruction serves two passes; the LUT steps are emitted once per pass.
-    const int P = jit_passes(lp);
-    const char* ut = P == 2 ? "u64" : "u32";
+    // One pass of 64 half-words (2,048 patterns) per loop iteration.
     o << "// exact simulation, " << n << " inputs: " << lp.lut_steps << " LUT steps, " << lp.scalar_steps
       << " scalar steps, " << lp.absorbed_gates << " gates absorbed into LUTs, " << lp.folded_gates << " folded, "
-      << P << " passes per iteration\n";
+      << 1 << " passes per iteration\n";
     o << "typedef unsigned int u32;\ntypedef unsigned long long u64;\n";
     o << "extern \"C\" __global__ void __launch_bounds__(" << block << ") __attribute__((amdgpu_waves_per_eu("
       << waves << ", " << waves << ")))\n";
@@ -107,10 +97,6 @@ std::string jit_source(const LutProgram& lp, int waves_per_eu, int block, int* w
     for (uint32_t i = 0; i < lp.words.size(); ++i) {
         std::snprintf(buf, sizeof buf, "  const u32 w%u = 0x%08Xu;\n", i, lp.words[i]);
         o << buf;
-        if (P == 2) {
-            std::snprintf(buf, sizeof buf, "  const u64 ww%u = 0x%08X%08Xull;\n", i, lp.words[i], lp.words[i]);
-            o << buf;
-        }
     }
     if (lds_slots) {  // per-wave spill area of the asm block: slot s of lane l at [s * 64 + l]
         o << "  __shared__ u32 fes_spill[" << (block / 64) * lds_slots * 64 << "];\n"
@@ -131,11 +117,11 @@ std::string jit_source(const LutProgram& lp, int waves_per_eu, int block, int* w
          "    const u64 b_first = __hip_atomic_load(best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);\n"
          "    u64 best_seen = ((u64)__builtin_amdgcn_readfirstlane((u32)(b_first >> 32)) << 32) |\n"
          "                    __builtin_amdgcn_readfirstlane((u32)b_first);\n"
-         "    for (u64 base = hw0; base < hw_stop; base += " << 64 * P << ") {\n"
+         "    for (u64 base = hw0; base < hw_stop; base += " << 64 << ") {\n"
          "      if (32ull * base >= best_seen) break;\n"
          "      // read for the next pass: the load completes while this pass runs\n"
          "      const u64 b_next = __hip_atomic_load(best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);\n";
-    if (P == 1 && specialized_emit_mode() == 1) {
+    if (specialized_emit_mode() == 1) {
         if (block_body.empty())
             o << "      // one asm block would need " << bs.vgprs << " VGPRs (" << bs.vgprs_min_live
               << " in the pressure-aware order) and " << bs.sgprs << " SGPRs\n";
@@ -149,26 +135,15 @@ std::string jit_source(const LutProgram& lp, int waves_per_eu, int block, int* w
     if (!block_body.empty()) {
         o << "      const u32 base_lo = (u32)base, base_hi = (u32)(base >> 32);\n" << block_body;
     } else {
-    for (uint32_t i = 11; i < n; ++i) {
-        if (P == 1)
-            o << "      const u32 x" << i << " = 0u - (u32)((base >> " << (i - 5) << ") & 1ull);\n";
-        else if (i == 11)  // bit 6 of the half-word index: clear in pass 0, set in pass 1 (base % 128 == 0)
-            o << "      const u64 x11 = 0xFFFFFFFF00000000ull;\n";
-        else
-            o << "      const u64 x" << i << " = 0ull - ((base >> " << (i - 5) << ") & 1ull);\n";
-    }
-    for (int q = 0; q < P; ++q) o << "      u32 m" << q << " = 0u;\n";
+    for (uint32_t i = 11; i < n; ++i)
+        o << "      const u32 x" << i << " = 0u - (u32)((base >> " << (i - 5) << ") & 1ull);\n";
+    o << "      u32 m0 = 0u;\n";
     // Every gate is an inline-asm instruction whose function the planner fixed, so the
     // compiler allocates registers and schedules but never rewrites the logic.  VALU
     // operands: at most one scalar (SGPR) source per instruction; others go through VGPRs.
-    auto scalar_name = [&](const LutRef& r) {  // a scalar-step operand (full P-pass register)
-        if (r.kind == LutRef::Word) return std::string(P == 2 ? "ww" : "w") + std::to_string(r.index);
-        return ref_name(r);
-    };
-    auto pass_name = [&](const LutRef& r, int q) {  // a LUT operand for pass q
+    auto scalar_name = [&](const LutRef& r) { return ref_name(r); };  // a scalar-step operand
+    auto pass_name = [&](const LutRef& r, int q) {                     // a LUT operand
         if (r.kind == LutRef::Varying) return "vr" + std::to_string(r.index) + "_" + std::to_string(q);
-        if (P == 2 && (r.kind == LutRef::Uniform || (r.kind == LutRef::Input && r.index >= 11)))
-            return "(u32)(" + ref_name(r) + (q ? " >> 32)" : ")");
         return ref_name(r);
     };
     // Runs of consecutive scalar steps are emitted as one asm block (the compiler pads every
@@ -191,7 +166,7 @@ std::string jit_source(const LutProgram& lp, int waves_per_eu, int block, int* w
                 const std::string nm = scalar_name(st->leaf[j]);
                 if (in_index(nm).empty()) ins.push_back(nm);
             }
-        const char* sfx = P == 2 ? "_b64" : "_b32";
+        const char* sfx = "_b32";
         std::string text;
         for (const LutStep* st : run) {
             const bool na = st->table & 1, nb = (st->table >> 1) & 1;
@@ -203,7 +178,7 @@ std::string jit_source(const LutProgram& lp, int waves_per_eu, int block, int* w
             text += std::string(text.empty() ? "" : "\\n\\t") + opname + sfx + " " +
                     in_index("su" + std::to_string(st->dst)) + ", " + a + ", " + b;
         }
-        o << "      " << ut;
+        o << "      u32";
         for (size_t i = 0; i < outs.size(); ++i) o << (i ? ", " : " ") << outs[i];
         o << ";\n      asm(\"" << text << "\" : ";
         for (size_t i = 0; i < outs.size(); ++i) o << (i ? ", " : "") << "\"=&s\"(" << outs[i] << ")";
@@ -231,7 +206,8 @@ std::string jit_source(const LutProgram& lp, int waves_per_eu, int block, int* w
             continue;
         }
         flush_scalar();
-        for (int q = 0; q < P; ++q) {
+        {
+            const int q = 0;
             if (st.op == LutStep::Lut) {
                 const uint32_t k = st.nleaves;
                 const char* ops = k == 3 ? "%1, %2, %3" : k == 2 ? "%1, %2, %2" : "%1, %1, %1";
@@ -260,10 +236,10 @@ std::string jit_source(const LutProgram& lp, int waves_per_eu, int block, int* w
     }
     flush_scalar();
     }
-    // Lowest failing pattern of this iteration: passes in ascending order, then the lowest
-    // lane, then the lowest bit.
+    // Lowest failing pattern of this pass: the lowest lane, then its lowest bit.
     o << "      u64 p = ~0ull;\n";
-    for (int q = P - 1; q >= 0; --q) {
+    {
+        const int q = 0;
         o << "      {\n"
              "        const u64 hw = base + " << 64 * q << "u + lane;\n"
              "        const u32 mq = (hw >= hw_begin && hw < hw_end) ? m" << q << " : 0u;\n"
@@ -359,7 +335,6 @@ std::shared_ptr<JitKernel> jit_kernel(Circuit& c, int waves_per_eu, double* comp
     std::lock_guard<std::mutex> g(k->mu);
     if (!k->code.empty()) return k;
     k->source = jit_source(c.lut_program(), waves_per_eu, k->block, &k->waves_used);
-    k->passes = jit_passes(c.lut_program());
     k->hash = fnv1a(k->source);
     {
         std::lock_guard<std::mutex> cg(g_cache_mu);
@@ -411,7 +386,7 @@ JitLaunchPlan jit_prepare(Device& dev, JitKernel& k, const HwRange& r, uint64_t 
     lp.grid = dev.prop.multiProcessorCount * blocks_per_cu;
     lp.block = k.block;
     const uint64_t waves = (uint64_t)lp.grid * (k.block / 64);
-    const uint64_t step = 64ull * (uint64_t)k.passes;  // half-words per loop iteration
+    const uint64_t step = 64;  // half-words per loop iteration (one pass)
     lp.hw_begin = r.begin;
     lp.hw_end = r.end;
     lp.hw_first = r.begin / step * step;

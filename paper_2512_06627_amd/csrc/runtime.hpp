@@ -38,7 +38,6 @@ struct JitKernel {
     int waves_per_eu = 2;  // requested occupancy (the cache key)
     int waves_used = 2;    // occupancy the source was built for (the launch grid follows it)
     int block = 256;
-    int passes = 1;  // 64-half-word passes per loop iteration; tiles are multiples of this
     double compile_ms = 0;
     std::mutex mu;
     std::map<int, std::pair<hipModule_t, hipFunction_t>> per_device;
@@ -169,7 +168,6 @@ int specialized_bank_aware();     // FASTLEC_ES_JIT_BANKS
 int specialized_vgpr_cap();       // FASTLEC_ES_JIT_VGPR_CAP: lower VGPR limit of the asm block (tests)
 int specialized_latency_slots();  // FASTLEC_ES_JIT_DIST
 int specialized_emit_mode();  // FASTLEC_ES_JIT_EMIT: 1 one asm block per pass, 0 one asm statement per gate
-int jit_passes(const LutProgram& lp);
 
 }  // namespace fes
 

@@ -214,7 +214,7 @@ void fastlec_es_server::step(const std::vector<Job*>& act) {
         Job* j = act[t];
         if (jk[t]) {  // specialized slice: about one step's worth at the kernel's rate
             const double per_hw = 32.0 * std::max<uint32_t>(1, j->c->plan1.num_gate_instrs);
-            const uint64_t step_hw = 64ull * (uint64_t)jk[t]->passes;
+            const uint64_t step_hw = 64;  // one pass of the specialized kernel
             uint64_t slice = (uint64_t)std::max(64.0 * (double)step_hw, std::floor(jit_rate * step_ms_target / 1e3 / per_hw));
             slice = (slice + step_hw - 1) / step_hw * step_hw;
             windows[t] = HwRange{j->cursor, std::min(j->range.end, j->cursor + slice)};

@@ -311,3 +311,13 @@ def test_wide_cones_specialized_vs_interpreter():
                 assert "LDS spill" in src
             print("wide cone", size, n, fault, flush=True)
             assert gpu_answer(c, kernel="specialized") == gpu_answer(c, kernel="interp"), (size, fault)
+
+
+def test_per_gate_fallback_emitter_matches_oracle(monkeypatch):
+    """The last-resort emitter (one asm statement per gate, compiler register allocation), used
+    when a cone is too wide even for LDS spill slots, forced here on stored workloads."""
+    monkeypatch.setenv("FASTLEC_ES_JIT_EMIT", "0")
+    for name in ("mult6_array_wallace_f1", "mult12_array_booth_f2", "mac8_fused_separate_f2"):
+        c = es.fastlec_es_load_aig(miters.workload(name).to_aig())
+        assert "one asm block" not in es.fastlec_es_specialized_source(c, 3)
+        assert gpu_answer(c, kernel="specialized") == expected(name), name
