@@ -222,18 +222,14 @@ void run_batch_graph(Device& dev, const std::vector<Circuit*>& cs, const std::ve
         Buffer b;
         ~Releaser() { d.release(b); }
     } rel{dev, res};
-    hipEvent_t e0, e1;
-    FES_HIP(hipEventCreate(&e0));
-    FES_HIP(hipEventCreate(&e1));
-    FES_HIP(hipEventRecord(e0, stream));
+    ScopedEvent e0, e1;
+    FES_HIP(hipEventRecord(e0.e, stream));
     FES_HIP(hipGraphLaunch(bg->exec, stream));
-    FES_HIP(hipEventRecord(e1, stream));
+    FES_HIP(hipEventRecord(e1.e, stream));
     FES_HIP(hipMemcpyAsync(res.host, (uint8_t*)bg->buf.dev + bg->best_off, 8 * k, hipMemcpyDeviceToHost, stream));
     FES_HIP(hipStreamSynchronize(stream));
     float t = 0;
-    if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) t = 0;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (hipEventElapsedTime(&t, e0.e, e1.e) != hipSuccess) t = 0;
     if (ms) *ms = t;
     best.assign((uint64_t*)res.host, (uint64_t*)res.host + k);
 }

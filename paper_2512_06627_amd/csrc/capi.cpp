@@ -67,13 +67,17 @@ void fill_result(const Circuit& c, const HwRange& r, uint64_t best, fastlec_es_r
     }
 }
 
-// Choose the kernel: the specialized one pays a compile (about a second) once per circuit,
-// so it is used when the space is large enough for that to be repaid.
-bool use_specialized(const Circuit& c, const fastlec_es_options& o, const HwRange& r) {
+// Choose the kernel: the specialized one pays a hipRTC compile once per circuit (about 0.2 s
+// plus 0.03 ms per gate), so without a compiled kernel it is used when the interpreter
+// (about 3e13 node*patterns/s) would take more than twice that; a compiled kernel is used
+// for any space beyond a launch's worth.
+bool use_specialized(Circuit& c, const fastlec_es_options& o, const HwRange& r) {
     if (o.kernel == FASTLEC_KERNEL_SPECIALIZED) return true;
     if (o.kernel != FASTLEC_KERNEL_AUTO) return false;
-    const double work = (double)c.plan1.num_gate_instrs * 32.0 * (double)(r.end - r.begin);
-    return work >= 1e12;
+    const double gates = std::max<uint32_t>(1, c.plan1.num_gate_instrs);
+    const double work = gates * 32.0 * (double)(r.end - r.begin);
+    if (jit_ready(c, specialized_waves_per_eu())) return work >= 1e11;
+    return work >= 3e13 * 2.0 * (0.2 + 3e-5 * gates);
 }
 
 void check_one(Circuit& c, const fastlec_es_options& o, fastlec_es_result* out) {

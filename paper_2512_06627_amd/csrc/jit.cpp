@@ -1,15 +1,16 @@
 // Specialized exact-simulation kernel: the circuit becomes straight-line code.
 //
-// The paper keeps the compiled instruction stream in the constant cache and
-// each thread's bit-vector registers in shared memory, and finds the kernel
-// bound by memory traffic (Section 3.3).  On gfx950 the circuit itself is
-// compiled into the kernel: every planner slot is a 32-bit register variable,
-// so a gate is one VALU operation on register operands (v_and_b32, v_bfi_b32
-// or v_bitop3_b32 for complemented fanins) and no node value ever leaves the
-// register file.  Primary inputs come from the pattern index: inputs 0..4 are
-// constants inside a 32-bit word, inputs 5..10 are lane bits, inputs 11.. are
-// bits of the wave's base index and so live in SGPRs, where gates whose
-// fanins are all wave-uniform run on the scalar unit.
+// The paper keeps the compiled instruction stream in the constant cache and each
+// thread's bit-vector registers in shared memory, and finds the kernel bound by memory
+// traffic (Section 3.3).  On gfx950 the circuit itself is compiled into the kernel: the
+// planner's LUT program (lut.cpp) becomes one inline-asm block per 2,048-pattern pass with
+// planner-assigned registers (emit_block.cpp), so a LUT of up to three inputs is one
+// v_bitop3_b32 and node values stay in registers (or, for very wide cones, LDS spill
+// slots).  Primary inputs come from the pattern index: inputs 0..4 are constants inside a
+// 32-bit word, inputs 5..10 are lane bits, inputs 11.. are bits of the wave's base index
+// (SGPR operands).  Around the block, plain HIP claims tiles, prefetches the early-exit
+// bound and reports the lowest failing pattern.  When no block fits, every gate becomes
+// its own asm statement and the compiler allocates registers.
 //
 // The source is compiled once per circuit with hipRTC for gfx950 and cached.
 #include <hip/hiprtc.h>
@@ -318,6 +319,15 @@ int specialized_scalar_policy() { return env_int("FASTLEC_ES_JIT_SCALAR", 2, 0, 
 int specialized_block() {
     const int b = env_int("FASTLEC_ES_JIT_BLOCK", 256, 64, 1024);
     return b % 64 ? 256 : b;
+}
+
+std::shared_ptr<JitKernel> jit_ready(Circuit& c, int waves_per_eu) {
+    std::lock_guard<std::mutex> g(c.mu);
+    auto it = c.jit.find(waves_per_eu);
+    if (it == c.jit.end()) return nullptr;
+    std::unique_lock<std::mutex> gk(it->second->mu, std::try_to_lock);
+    if (!gk.owns_lock()) return nullptr;
+    return it->second->code.empty() ? nullptr : it->second;
 }
 
 std::shared_ptr<JitKernel> jit_kernel(Circuit& c, int waves_per_eu, double* compile_ms) {

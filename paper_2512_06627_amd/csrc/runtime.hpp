@@ -23,6 +23,17 @@ namespace fes {
         if (e_ != hipSuccess) ::fes::throw_hip(e_, #call); \
     } while (0)
 
+// A HIP event owned by a scope (destroyed on every exit path, errors included).
+struct ScopedEvent {
+    hipEvent_t e = nullptr;
+    ScopedEvent() { FES_HIP(hipEventCreate(&e)); }
+    ~ScopedEvent() {
+        if (e) (void)hipEventDestroy(e);
+    }
+    ScopedEvent(const ScopedEvent&) = delete;
+    ScopedEvent& operator=(const ScopedEvent&) = delete;
+};
+
 double now_ms();
 
 // Opt-in trace of host phases to stderr (environment FASTLEC_ES_TRACE=1).
@@ -133,6 +144,9 @@ int specialized_waves_per_eu();
 int specialized_block();
 int specialized_scalar_policy();  // FASTLEC_ES_JIT_SCALAR: 0 all, 1 pure uniform only, 2 none
 std::shared_ptr<JitKernel> jit_kernel(Circuit& c, int waves_per_eu, double* compile_ms);
+// The circuit's specialized kernel if it is already compiled, else null.  Never compiles and
+// never waits: a kernel whose compile is in progress counts as not ready.
+std::shared_ptr<JitKernel> jit_ready(Circuit& c, int waves_per_eu);
 void run_jit(Device& dev, Circuit& c, JitKernel& k, const HwRange& r, uint64_t tile_hw, hipStream_t stream,
              const int* cancel, uint64_t* best, double* kernel_ms);
 // The same launch in two parts, for callers that keep `best` and the claim counter in their

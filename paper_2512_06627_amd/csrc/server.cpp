@@ -2,7 +2,8 @@
 //
 // Jobs are admitted by memory charge (peak live slots x words in flight x 8 B)
 // against a budget, and every step is one interpreter launch over the next
-// pattern slice of every job in flight.  A job that arrives while others are on
+// pattern slice of every job in flight (plus one launch per job on the specialized
+// tier, below).  A job that arrives while others are on
 // the device joins them at the next step; a job retires as soon as its answer
 // is final, and its charge goes back to the budget.  Slices are sized so a
 // step takes about FASTLEC_ES_SERVER_STEP_MS milliseconds (default 10), from a
@@ -109,19 +110,6 @@ struct fastlec_es_server {
     void finish(Job* j, double now);
 };
 
-namespace {
-// The circuit's specialized kernel if it is already compiled.  Never compiles and never
-// waits: a kernel whose compile is in progress holds its lock and counts as not ready.
-std::shared_ptr<JitKernel> compiled_kernel(Circuit& c, int waves) {
-    std::lock_guard<std::mutex> g(c.mu);
-    auto it = c.jit.find(waves);
-    if (it == c.jit.end()) return nullptr;
-    std::unique_lock<std::mutex> gk(it->second->mu, std::try_to_lock);
-    if (!gk.owns_lock()) return nullptr;
-    return it->second->code.empty() ? nullptr : it->second;
-}
-}  // namespace
-
 void fastlec_es_server::compile_loop() {
     for (;;) {
         Job* j = nullptr;
@@ -162,7 +150,7 @@ void fastlec_es_server::plan_tiers(const std::vector<Job*>& act) {
     std::lock_guard<std::mutex> g(mu);
     for (Job* j : act) {
         if (j->jit || j->compile_queued) continue;
-        if (auto k = compiled_kernel(*j->c, specialized_waves_per_eu())) {
+        if (auto k = jit_ready(*j->c, specialized_waves_per_eu())) {
             j->jit = k;
             continue;
         }
@@ -269,10 +257,8 @@ void fastlec_es_server::step(const std::vector<Job*>& act) {
         if (!g.c->empty())
             FES_HIP(hipMemcpyAsync(devp + g.desc_off, host + g.desc_off, sizeof(ConeDesc) * g.c->size(),
                                    hipMemcpyHostToDevice, stream));
-    hipEvent_t e0, e1;
-    FES_HIP(hipEventCreate(&e0));
-    FES_HIP(hipEventCreate(&e1));
-    FES_HIP(hipEventRecord(e0, stream));
+    ScopedEvent e0, e1, e2;
+    FES_HIP(hipEventRecord(e0.e, stream));
     for (Group& g : groups) {
         if (g.c->empty()) continue;
         InterpLaunch L;
@@ -286,9 +272,8 @@ void fastlec_es_server::step(const std::vector<Job*>& act) {
         L.cancel = nullptr;
         FES_HIP(launch_interp(L, g.sch.K, g.sch.B, g.sch.lds, g.sch.grid, g.sch.block, stream));
     }
-    FES_HIP(hipEventRecord(e1, stream));
+    FES_HIP(hipEventRecord(e1.e, stream));
     // Specialized slices: own claim counter per slot (zeroed first), shared best[] entry.
-    hipEvent_t e2 = nullptr;
     double jit_np = 0;
     if (!jit_jobs.empty()) {
         uint64_t* hc = (uint64_t*)(host + off_ctl_jit);
@@ -301,19 +286,13 @@ void fastlec_es_server::step(const std::vector<Job*>& act) {
                         nullptr, stream);
             jit_np += 32.0 * std::max<uint32_t>(1, j->c->plan1.num_gate_instrs) * (double)(windows[t].end - windows[t].begin);
         }
-        FES_HIP(hipEventCreate(&e2));
-        FES_HIP(hipEventRecord(e2, stream));
+        FES_HIP(hipEventRecord(e2.e, stream));
     }
     FES_HIP(hipMemcpyAsync(host + off_best, devp + off_best, 8ull * kCapacity, hipMemcpyDeviceToHost, stream));
     FES_HIP(hipStreamSynchronize(stream));
     float ms = 0, jit_ms = 0;
-    FES_HIP(hipEventElapsedTime(&ms, e0, e1));
-    if (e2) {
-        FES_HIP(hipEventElapsedTime(&jit_ms, e1, e2));
-        (void)hipEventDestroy(e2);
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    FES_HIP(hipEventElapsedTime(&ms, e0.e, e1.e));
+    if (!jit_jobs.empty()) FES_HIP(hipEventElapsedTime(&jit_ms, e1.e, e2.e));
     if (n_interp && ms > 0.5f) rate = 0.7 * rate + 0.3 * (step_np / (ms / 1e3));
     if (jit_np > 0 && jit_ms > 0.5f) jit_rate = 0.7 * jit_rate + 0.3 * (jit_np / (jit_ms / 1e3));
 
