@@ -190,7 +190,7 @@ int fastlec_es_compile_specialized(const fastlec_es_circuit *c, int waves_per_eu
  * to fit) and return the length it needs including the NUL.  buf may be NULL. */
 size_t fastlec_es_specialized_source(const fastlec_es_circuit *c, int waves_per_eu, char *buf, size_t len);
 
-/* Replay the interpreter instruction stream planned with `bundle` (1, 4 or 8) on the host,
+/* Replay the interpreter instruction stream planned with `bundle` (1, 4, 8 or 16) on the host,
  * with the kernels' bundle semantics, for the 32-pattern half-words hw .. hw+count-1
  * (half-word h holds patterns 32h .. 32h+31, bit j = pattern 32h+j).  out: count host
  * words of miter values.  Checks the plan's slot map first (FASTLEC_ERR_INVALID if broken). */

@@ -68,8 +68,9 @@ Schedule autotune(Device& dev, const std::vector<Circuit*>& cs, const std::vecto
     }
     std::vector<Schedule> cands;
     for (int K : {1, 2, 4})
-        for (int B : {4, 8})
+        for (int B : {4, 8, 16})
             for (int block : {64, 128, 256}) {
+                if (B == 16 && K > 2) continue;  // 16 bundles of 4 words per lane spill registers
                 Schedule s;
                 if (make_schedule(dev, cs, K, B, block, !hbm, s)) cands.push_back(s);
             }

@@ -188,6 +188,7 @@ hipError_t launch_k(const InterpLaunch& L, int B, bool lds, int grid, int block,
         case 1: return launch_kb<K, 1>(L, lds, grid, block, s);
         case 4: return launch_kb<K, 4>(L, lds, grid, block, s);
         case 8: return launch_kb<K, 8>(L, lds, grid, block, s);
+        case 16: return launch_kb<K, 16>(L, lds, grid, block, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -44,7 +44,7 @@ struct InterpLaunch {
 };
 
 // Launch the interpreter.  K = half-words per lane per row (1, 2, 4); B = bundle size
-// (1, 4, 8); lds = value file in LDS (else in hbm_rows).  Returns hipSuccess or an error.
+// (1, 4, 8, 16); lds = value file in LDS (else in hbm_rows).  Returns hipSuccess or an error.
 hipError_t launch_interp(const InterpLaunch& L, int K, int B, bool lds, int grid, int block,
                          hipStream_t stream);
 

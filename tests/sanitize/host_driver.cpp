@@ -32,7 +32,7 @@ int main(int argc, char** argv) {
             continue;
         }
         const Plan p1 = make_plan(g, Order::Auto, 1);
-        for (uint32_t b : {1u, 4u, 8u}) {
+        for (uint32_t b : {1u, 4u, 8u, 16u}) {
             const Plan p = b == 1 ? p1 : make_plan(g, Order::Auto, b);
             const std::string err = validate_plan(g, p);
             if (!err.empty()) {

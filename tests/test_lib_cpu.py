@@ -81,7 +81,7 @@ def _replay_vs_oracle(g, bundle, halfwords):
         assert word == int(sum(int(b) << j for j, b in enumerate(bits))), (hw, bundle)
 
 
-@pytest.mark.parametrize("bundle", [1, 4, 8])
+@pytest.mark.parametrize("bundle", [1, 4, 8, 16])
 def test_plan_replay_matches_oracle(bundle):
     rng = miters.SplitMix64(bundle)
     for name in ("mult6_array_wallace_f1", "mult12_array_booth_f3", "mac8_fused_separate_f1"):

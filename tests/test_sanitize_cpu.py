@@ -1,6 +1,6 @@
 """The host-side planner path built with AddressSanitizer and UndefinedBehaviorSanitizer.
 
-tests/sanitize/host_driver.cpp runs the AIGER reader, the slot planner (bundles 1, 4, 8, each
+tests/sanitize/host_driver.cpp runs the AIGER reader, the slot planner (bundles 1, 4, 8, 16, each
 validated by symbolic replay), the LUT mapper (scalar-unit and all-VALU policies) and the block
 emitter (all option combinations) on every file, and prints the LUT program's miter words at
 chosen half-words; those must equal the oracle's.  Host code only: nothing here runs on a GPU.
