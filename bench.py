@@ -178,6 +178,10 @@ def serve_leg(es, stream, seed: int = 5, seconds: float = 30.0, max_requests: in
         alone[k] = r["cex"] if r["verdict"] == es.FASTLEC_NONEQUIVALENT else None
     served = [r["cex"] if r["verdict"] == es.FASTLEC_NONEQUIVALENT else None for r in results]
     lat = sorted(r["latency_ms"] for r in results)
+    slow = sorted(range(len(results)), key=lambda i: -results[i]["latency_ms"])[:3]
+    slowest = [{"n": circs[which[i]].info()["num_pis"], "gates": gates[which[i]],
+                "latency_ms": round(results[i]["latency_ms"], 1), "queued_ms": round(results[i]["queued_ms"], 1),
+                "device_ms": round(results[i]["kernel_ms"], 1), "work": works[which[i]]} for i in slow]
     q = lambda f: lat[min(len(lat) - 1, int(f * len(lat)))]
     done_work = sum(works[k] for k in which)
     return {"requests": len(tickets), "arrival_rate_per_s": lam, "offered_load": load,
@@ -187,6 +191,7 @@ def serve_leg(es, stream, seed: int = 5, seconds: float = 30.0, max_requests: in
             "peak_charge_bytes": st["peak_charge_bytes"], "budget_bytes": st["budget_bytes"],
             "server_device_bytes": st["device_bytes"], "steps": st["steps"] - steps0,
             "specialized_slices": st["specialized_slices"], "latency_ms_p90": q(0.90), "latency_ms_max": lat[-1],
+            "slowest": slowest,
             "each_equal_alone": served == [alone[k] for k in which], "pool": pool, "generate_s": gen_s}
 
 

@@ -148,16 +148,21 @@ void fastlec_es_server::compile_loop() {
 void fastlec_es_server::plan_tiers(const std::vector<Job*>& act) {
     if (jit_mode == 0) return;
     std::lock_guard<std::mutex> g(mu);
+    // Jobs on the interpreter share each step's work equally, so one job's remaining time is
+    // its remaining work over its share of the interpreter's rate.
+    size_t sharing = 0;
+    for (Job* j : act) sharing += j->jit ? 0 : 1;
+    const double job_rate = rate / (double)std::max<size_t>(1, sharing);
     for (Job* j : act) {
         if (j->jit || j->compile_queued) continue;
         if (auto k = jit_ready(*j->c, specialized_waves_per_eu())) {
             j->jit = k;
             continue;
         }
-        // Remaining interpreter time vs compile time (hipRTC: about 0.2 s plus 0.03 ms per AND
-        // gate for these kernels; compiles run one at a time).
+        // Remaining interpreter time at this job's share vs compile time (hipRTC: about 0.2 s
+        // plus 0.03 ms per AND gate for these kernels; compiles run one at a time).
         const double gates = std::max<uint32_t>(1, j->c->plan1.num_gate_instrs);
-        const double interp_s = 32.0 * gates * (double)(j->range.end - j->cursor) / rate;
+        const double interp_s = 32.0 * gates * (double)(j->range.end - j->cursor) / job_rate;
         const double compile_s = 0.2 + 3e-5 * gates;
         if (jit_mode == 2 || interp_s > 2.0 * compile_s + 0.5) {
             j->compile_queued = true;
