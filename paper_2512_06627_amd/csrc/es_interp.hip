@@ -102,8 +102,10 @@ __global__ void __launch_bounds__(1024) es_interp_kernel(InterpLaunch L) {
         const uint32_t n = c->n_inputs, n_instr = c->n_instr;
         const FES_CONST Instr* prog = as_const(c->prog);
 
+        // The bound found by other waves is read once per work item: a device-scope load at
+        // the start of every pass is a full memory round trip per pass.
+        const uint64_t best_now = uniform64(__hip_atomic_load(best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         for (uint64_t base = hw0; base < hw_stop; base += 64u * K) {
-            const uint64_t best_now = uniform64(__hip_atomic_load(best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
             if (32u * base >= best_now) break;  // nothing at or above here can lower best
             V zero;
 #pragma unroll
