@@ -118,11 +118,19 @@ std::string jit_source(const LutProgram& lp, int waves_per_eu, int block, int* w
          "    const u64 b_first = __hip_atomic_load(best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);\n"
          "    const u64 best_seen = ((u64)__builtin_amdgcn_readfirstlane((u32)(b_first >> 32)) << 32) |\n"
          "                    __builtin_amdgcn_readfirstlane((u32)b_first);\n"
-         "    for (u64 base = hw0; base < hw_stop; base += " << 64 << ") {\n"
-         "      if (32ull * base >= best_seen) break;\n";
+         "    // passes of this tile that start below the bound (pattern 32*base < best_seen)\n"
+         "    const u64 bound_hw = best_seen / 32u + ((best_seen & 31u) ? 1u : 0u);\n"
+         "    const u64 stop = hw_stop < bound_hw ? hw_stop : bound_hw;\n"
+         "    const u32 npass = stop > hw0 ? (u32)((stop - hw0 + 63u) / 64u) : 0u;\n"
+         "    for (u32 t = 0; t < npass; ++t) {\n"
+         "      const u64 base = hw0 + 64ull * t;\n";
     // The bound found by other waves is read once per tile (up to 64 passes): a device-scope
     // load each pass cost 15% (16x16 miter) to 37% (MAC8) of the kernel time, and after a
-    // failure is found a wave finishes at most its current tile.
+    // failure is found a wave finishes at most its current tile.  The pass loop runs on a
+    // 32-bit counter (gfx9 has no scalar 64-bit ordered compare, so 64-bit loop tests became
+    // vector compares).  Only the range's first and last pass can hold half-words outside it
+    // (hw_first is hw_begin rounded down to a pass), so the range mask is applied inside the
+    // branch taken when some lane fails: a failure outside the range is dropped there.
     if (specialized_emit_mode() == 1) {
         if (block_body.empty())
             o << "      // one asm block would need " << bs.vgprs << " VGPRs (" << bs.vgprs_min_live
@@ -238,22 +246,21 @@ std::string jit_source(const LutProgram& lp, int waves_per_eu, int block, int* w
     }
     flush_scalar();
     }
-    // Lowest failing pattern of this pass: the lowest lane, then its lowest bit.
-    o << "      u64 p = ~0ull;\n";
-    {
-        const int q = 0;
-        o << "      {\n"
-             "        const u64 hw = base + " << 64 * q << "u + lane;\n"
-             "        const u32 mq = (hw >= hw_begin && hw < hw_end) ? m" << q << " : 0u;\n"
-             "        const u64 bal = __ballot(mq != 0u);\n"
-             "        const u32 l = bal ? (u32)__builtin_ctzll(bal) : 0u;\n"
-             "        const u32 ml = __builtin_amdgcn_readlane(mq, l);\n"
-             "        if (bal) p = 32ull * (base + " << 64 * q << "u + l) + (u32)__builtin_ctz(ml);\n"
-             "      }\n";
-    }
-    o << "      if (p != ~0ull) {\n"
-         "        atomicMin(best, p);\n"
-         "        break;\n"
+    // Lowest failing pattern of this pass: the lowest lane, then its lowest bit; all of it
+    // under a wave-uniform branch on the ballot.
+    o << "      u64 bal = __ballot(m0 != 0u);\n"
+         "      if (bal) {\n"
+         "        u64 b = base;\n"
+         "        asm volatile(\"\" : \"+s\"(b));  // keeps the loop from carrying the edge offsets\n"
+         "        const u32 lo = b < hw_begin ? (u32)(hw_begin - b) : 0u;\n"
+         "        const u64 left = hw_end - b;\n"
+         "        bal &= (~0ull << lo) & (left >= 64u ? ~0ull : (1ull << left) - 1u);\n"
+         "        if (bal) {\n"
+         "          const u32 l = (u32)__builtin_ctzll(bal);\n"
+         "          const u32 ml = __builtin_amdgcn_readlane(m0, l);\n"
+         "          atomicMin(best, 32ull * (base + l) + (u32)__builtin_ctz(ml));\n"
+         "          break;\n"
+         "        }\n"
          "      }\n";
     o << "    }\n"
          "  }\n"
