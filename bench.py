@@ -34,8 +34,8 @@ PEAK_NODE_PATTERNS = PEAK_LANE_OPS * 32                   # 2.52e15 AND-node*pat
 # WRITE_SIZE (each scaled by what the counter reads for a device copy of known size; summary
 # and commands in profiles/es_specialized_mult16_counters.md).  Valid only for the kernel whose
 # generated source has this SHA-256; any other kernel reports null.
-PROFILED_TRAFFIC = {"source_sha256": "87f987584ee5f467681e38e0041c55c7e932825ed6cae8611f867e224280e7c0",
-                    "bytes_per_launch": 2943152}
+PROFILED_TRAFFIC = {"source_sha256": "9fae5f35b5a1ef213fec8f5f551f4b63918c0ec8fc30876f31e7d763a86db6ed",
+                    "bytes_per_launch": 2944953}
 
 
 def profiled_traffic(es, c):
