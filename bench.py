@@ -28,6 +28,7 @@ CUS, LANES_PER_CYCLE, CLOCK_HZ = 256, 128, 2.4e9
 PEAK_LANE_OPS = CUS * LANES_PER_CYCLE * CLOCK_HZ        # 7.86e13 int32 lane-ops/s
 PEAK_WAVE_INSTR = PEAK_LANE_OPS / 64                     # 1.23e12 wave64 VALU instructions/s
 PEAK_NODE_PATTERNS = PEAK_LANE_OPS * 32                   # 2.52e15 AND-node*patterns/s
+PEAK_HBM = 8.0e12                                        # bytes/s, MI355X HBM3E
 
 
 # HBM bytes per launch of the 16x16 miter's specialized kernel, from rocprofv3 FETCH_SIZE and
@@ -125,6 +126,48 @@ def batch_leg(es, stream, seed: int = 4, count: int = 256, faulty: int = 26, n_r
             "batched_cones_per_s": count / t_batch, "batched_vs_plain_speedup": t_plain / t_batch,
             "identical_verdicts": plain == plain2 == first == got, "first_batch_call_s": t_first,
             "generate_s": gen_s}
+
+
+def rsim_leg(es, stream, workload: str = "mult16_array_booth", words: int = 1 << 18, reps: int = 5):
+    """Random-pattern simulation (sweeping step 1) on the headline miter: every variable's
+    signature row over `words` 32-bit columns of seeded random input words, then the
+    signature hashes and the candidate classes.  Both kernels are bound by HBM: the
+    simulation writes (max_var + 1) x words x 4 bytes and reads n x words x 4; the hash
+    kernel reads the signature matrix once."""
+    import numpy as np
+    import torch
+    import miters
+    g = miters.workload(workload)
+    c = es.fastlec_es_load_aig(g.to_aig())
+    info = c.info()
+    n, V = info["num_pis"], info["num_pis"] + info["num_ands"]
+    rng = np.random.default_rng(8)
+    pi = torch.from_numpy(rng.integers(0, 1 << 32, size=(n, words), dtype=np.uint64).astype(np.uint32)
+                          .view(np.int32)).cuda()
+    sig = torch.empty((V + 1, words), dtype=torch.int32, device="cuda")
+    h = torch.empty(V + 1, dtype=torch.int64, device="cuda")
+    ones = torch.empty(V + 1, dtype=torch.int64, device="cuda")
+    es.fastlec_es_simulate(c, pi, words, sig, stream=stream)
+    es.fastlec_es_signature_hash(sig, V + 1, words, h, ones, stream=stream)
+    sim_ms = sorted(es.fastlec_es_simulate(c, pi, words, sig, stream=stream) for _ in range(reps))[reps // 2]
+    hash_ms = sorted(es.fastlec_es_signature_hash(sig, V + 1, words, h, ones, stream=stream)
+                     for _ in range(reps))[reps // 2]
+    t0 = time.perf_counter()
+    cls = es.fastlec_es_classes(h.cpu().numpy().view(np.uint64))
+    classes_ms = (time.perf_counter() - t0) * 1e3
+    sizes = np.bincount(cls)
+    sim_bytes = (V + 1) * words * 4 + n * words * 4
+    hash_bytes = (V + 1) * words * 4
+    del sig
+    torch.cuda.empty_cache()
+    return {"workload": workload, "words": words, "patterns": 32 * words, "rows": V + 1,
+            "simulate_ms": sim_ms, "simulate_GBps": sim_bytes / (sim_ms / 1e3) / 1e9,
+            "simulate_hbm_frac": sim_bytes / (sim_ms / 1e3) / PEAK_HBM,
+            "simulate_node_patterns_per_s": info["num_ands"] * 32 * words / (sim_ms / 1e3),
+            "hash_ms": hash_ms, "hash_GBps": hash_bytes / (hash_ms / 1e3) / 1e9,
+            "hash_hbm_frac": hash_bytes / (hash_ms / 1e3) / PEAK_HBM,
+            "classes_host_ms": classes_ms, "classes_with_2_or_more": int((sizes >= 2).sum()),
+            "rows_in_such_classes": int(sizes[sizes >= 2].sum())}
 
 
 def serve_leg(es, stream, seed: int = 5, seconds: float = 30.0, max_requests: int = 400,
@@ -299,6 +342,8 @@ def main():
         sec["batch_small"] = batch_leg(es, stream, seed=6, count=2048, faulty=205, n_range=(8, 16),
                                        size_range=(50, 2000))
         print(json.dumps({"progress": "batch_small", **sec["batch_small"]}), file=sys.stderr, flush=True)
+        sec["rsim"] = rsim_leg(es, stream)
+        print(json.dumps({"progress": "rsim", **sec["rsim"]}), file=sys.stderr, flush=True)
         sec["serve"] = serve_leg(es, stream, seconds=a.serve_seconds)
         out["secondary"] = sec
     print(json.dumps(out), flush=True)

@@ -177,6 +177,43 @@ int fastlec_es_server_stats_get(fastlec_es_server *s, fastlec_es_server_stats *s
 /* Stop the server thread and free its memory; pending jobs are dropped. */
 void fastlec_es_server_destroy(fastlec_es_server *s);
 
+/* ---- random-pattern simulation (candidate equivalences for sweeping) ------- */
+
+/* Logic simulation that opens a sweeping flow: simulate the circuit on given input words
+ * and find potentially equivalent (PE) nodes (paper, Section 2.3, step 1; its stability
+ * and entropy features, Section 3.2, come from the same simulation).
+ *
+ * fastlec_es_simulate: the value of every variable of c on num_words columns of input words.
+ *   pi_words  device pointer, n rows of num_words 32-bit words, row-major (row i = input i;
+ *             bit j of word k = the input's value in simulated pattern 32k + j).  Caller-owned,
+ *             read only.  May be NULL when n = 0.
+ *   sig       device pointer, (max_var + 1) rows of num_words words, row-major, caller-owned,
+ *             written completely: row 0 = constant false, rows 1..n = the input words, row
+ *             n+1+k = AND gate k of the file (variables renumbered as in the loaded circuit:
+ *             the file's own numbering when its inputs are variables 1..n and its AND gates
+ *             n+1..M in order).  Every AND gate is simulated, also gates outside the outputs'
+ *             cone.  max_var = num_pis + num_ands (fastlec_es_info).
+ *   opts      device, stream, words_per_thread, wg_size and kernel (FASTLEC_KERNEL_INTERP_HBM
+ *             forces value files in device memory) are honoured; may be NULL.
+ *   kernel_ms if not NULL, the kernel's time (HIP events on the launch stream).
+ * Blocks until sig is written.  FASTLEC_ERR_INVALID for null pointers or num_words = 0.
+ *
+ * fastlec_es_signature_hash: per row r of a signature matrix (device, rows x num_words,
+ *   row-major): ones[r] = number of 1 bits; hash[r] = sum over words k of
+ *   word'_k * (fmix32(k mod 2^32) | 1) mod 2^64, where word' is the row complemented when
+ *   bit 0 of its word 0 is 1 (so a node and its complement hash alike) and fmix32 is the
+ *   MurmurHash3 32-bit finaliser.  hash and ones: device pointers, rows entries each,
+ *   caller-owned.  Blocks until written.
+ *
+ * fastlec_es_classes: host arrays.  class_of[r] = the lowest row whose hash equals hash[r]
+ *   (the class representative; a row is PE with its representative, with complement
+ *   iff their rows differ in bit 0 of word 0). */
+int fastlec_es_simulate(const fastlec_es_circuit *c, const uint32_t *pi_words, uint64_t num_words, uint32_t *sig,
+                        const fastlec_es_options *opts, double *kernel_ms);
+int fastlec_es_signature_hash(const uint32_t *sig, uint64_t rows, uint64_t num_words, uint64_t *hash, uint64_t *ones,
+                              const fastlec_es_options *opts, double *kernel_ms);
+int fastlec_es_classes(const uint64_t *hash, uint64_t rows, uint32_t *class_of);
+
 /* ---- diagnostics (no GPU needed) ------------------------------------------ */
 
 /* Compile the specialized kernel of c for gfx950 with hipRTC (cached per circuit and by

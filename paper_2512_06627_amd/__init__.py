@@ -105,6 +105,12 @@ SIGNATURES = [
                                               ctypes.POINTER(ctypes.c_uint32)]),
     ("fastlec_es_host_replay_specialized", ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_uint64,
                                                           ctypes.POINTER(ctypes.c_uint32)]),
+    ("fastlec_es_simulate", ctypes.c_int, [_P, _P, ctypes.c_uint64, _P, ctypes.POINTER(fastlec_es_options),
+                                           ctypes.POINTER(ctypes.c_double)]),
+    ("fastlec_es_signature_hash", ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_uint64, _P, _P,
+                                                 ctypes.POINTER(fastlec_es_options), ctypes.POINTER(ctypes.c_double)]),
+    ("fastlec_es_classes", ctypes.c_int, [ctypes.POINTER(ctypes.c_uint64), ctypes.c_uint64,
+                                          ctypes.POINTER(ctypes.c_uint32)]),
 ]
 
 _lib = None
@@ -256,6 +262,47 @@ def fastlec_es_host_replay_specialized(circuit: Circuit, hw: int, count: int):
     if rc:
         _raise(rc)
     return list(out)
+
+
+def _device_ptr(x):
+    """Device address of a torch tensor (or an integer address)."""
+    return x if isinstance(x, int) else x.data_ptr()
+
+
+def fastlec_es_simulate(circuit: Circuit, pi_words, num_words: int, sig, **opts) -> float:
+    """Value of every variable on num_words columns of input words (device buffers: pi_words
+    n x num_words uint32, sig (max_var + 1) x num_words uint32); returns the kernel time in ms."""
+    o = options(**opts)
+    ms = ctypes.c_double()
+    rc = lib().fastlec_es_simulate(circuit.handle, _device_ptr(pi_words) if pi_words is not None else None,
+                                   num_words, _device_ptr(sig), ctypes.byref(o), ctypes.byref(ms))
+    if rc:
+        _raise(rc)
+    return ms.value
+
+
+def fastlec_es_signature_hash(sig, rows: int, num_words: int, hash, ones, **opts) -> float:
+    """Complement-normalised hash and number of ones of every row (device buffers); returns
+    the kernel time in ms."""
+    o = options(**opts)
+    ms = ctypes.c_double()
+    rc = lib().fastlec_es_signature_hash(_device_ptr(sig), rows, num_words, _device_ptr(hash), _device_ptr(ones),
+                                         ctypes.byref(o), ctypes.byref(ms))
+    if rc:
+        _raise(rc)
+    return ms.value
+
+
+def fastlec_es_classes(hashes):
+    """numpy uint32 array: the lowest row with the same hash as each row (host arrays)."""
+    import numpy as np
+    h = np.ascontiguousarray(np.asarray(hashes, dtype=np.uint64))
+    out = np.zeros(h.size, dtype=np.uint32)
+    rc = lib().fastlec_es_classes(h.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), h.size,
+                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+    if rc:
+        _raise(rc)
+    return out
 
 
 class Server:

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <unordered_map>
 #include <fstream>
 #include <sstream>
 
@@ -333,6 +334,53 @@ int fastlec_es_host_replay(const fastlec_es_circuit* c, uint32_t bundle, uint64_
             }
             out[t] = m;
         }
+        return FASTLEC_OK;
+    });
+}
+
+int fastlec_es_simulate(const fastlec_es_circuit* c, const uint32_t* pi_words, uint64_t num_words, uint32_t* sig,
+                        const fastlec_es_options* opts, double* kernel_ms) {
+    return guarded([&] {
+        if (!c || !sig || num_words == 0) throw Error{kErrInvalid, "null circuit or signature, or no words"};
+        Circuit& cc = const_cast<Circuit&>(c->c);
+        if (cc.aig.num_inputs && !pi_words) throw Error{kErrInvalid, "null input words"};
+        fastlec_es_options o = opts ? *opts : defaults();
+        Device& dev = device(o.device);
+        hipStream_t stream = o.hip_stream ? (hipStream_t)o.hip_stream : dev.stream;
+        run_sim(dev, cc, pi_words, num_words, sig, &o, stream, kernel_ms);
+        return FASTLEC_OK;
+    });
+}
+
+int fastlec_es_signature_hash(const uint32_t* sig, uint64_t rows, uint64_t num_words, uint64_t* hash, uint64_t* ones,
+                              const fastlec_es_options* opts, double* kernel_ms) {
+    return guarded([&] {
+        if (!sig || !hash || !ones || rows == 0 || num_words == 0) throw Error{kErrInvalid, "null pointer or empty matrix"};
+        fastlec_es_options o = opts ? *opts : defaults();
+        Device& dev = device(o.device);
+        hipStream_t stream = o.hip_stream ? (hipStream_t)o.hip_stream : dev.stream;
+        // One wave per row; enough workgroups of four waves for eight per CU, fewer for few rows.
+        const uint64_t want = (rows + 3) / 4;
+        const int grid = (int)std::min<uint64_t>(want, (uint64_t)dev.prop.multiProcessorCount * 8);
+        ScopedEvent e0, e1;
+        FES_HIP(hipEventRecord(e0.e, stream));
+        FES_HIP(launch_signature_hash(sig, rows, num_words, hash, ones, grid, stream));
+        FES_HIP(hipEventRecord(e1.e, stream));
+        FES_HIP(hipStreamSynchronize(stream));
+        float ms = 0;
+        FES_HIP(hipEventElapsedTime(&ms, e0.e, e1.e));
+        if (kernel_ms) *kernel_ms = ms;
+        return FASTLEC_OK;
+    });
+}
+
+int fastlec_es_classes(const uint64_t* hash, uint64_t rows, uint32_t* class_of) {
+    return guarded([&] {
+        if (rows && (!hash || !class_of)) throw Error{kErrInvalid, "null pointer"};
+        if (rows > UINT32_MAX) throw Error{kErrInvalid, "more than 2^32 - 1 rows"};
+        std::unordered_map<uint64_t, uint32_t> first;
+        first.reserve(rows);
+        for (uint64_t r = 0; r < rows; ++r) class_of[r] = first.emplace(hash[r], (uint32_t)r).first->second;
         return FASTLEC_OK;
     });
 }

@@ -23,6 +23,14 @@
 // folded into best[] with atomicMin.  The paper's ES checks every assignment
 // and reports a distinguishing pattern (Sections 2.1, 2.2, 3.3); this kernel
 // reports the lowest one, which makes the answer independent of scheduling.
+//
+// Simulation mode (kSim): the logic simulation that opens a sweeping flow
+// (Section 2.3, step 1).  The "half-word" index is a column of caller input
+// words: input i's row holds sim_pi[i][column] instead of the pattern-index
+// mask, each gate instruction's flags name the variable it defines, and its
+// value is stored to that variable's signature row.  Rows 0..n of the
+// signature are written too (constant false, the input words), so the output
+// is the value of every variable.  No miter, no early exit.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -62,7 +70,7 @@ __device__ __forceinline__ uint32_t pi_word(uint32_t i, uint64_t hw) {
     }
 }
 
-template <int K, int B, bool kLds>
+template <int K, int B, bool kLds, bool kSim>
 __global__ void __launch_bounds__(1024) es_interp_kernel(InterpLaunch L) {
     extern __shared__ uint32_t lds_file[];
     const uint32_t lane = threadIdx.x & 63u;
@@ -104,17 +112,34 @@ __global__ void __launch_bounds__(1024) es_interp_kernel(InterpLaunch L) {
 
         // The bound found by other waves is read once per work item: a device-scope load at
         // the start of every pass is a full memory round trip per pass.
-        const uint64_t best_now = uniform64(__hip_atomic_load(best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        const uint64_t best_now =
+            kSim ? ~0ull : uniform64(__hip_atomic_load(best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        const uint64_t W = L.sim_words;
         for (uint64_t base = hw0; base < hw_stop; base += 64u * K) {
             if (32u * base >= best_now) break;  // nothing at or above here can lower best
             V zero;
 #pragma unroll
             for (int j = 0; j < K; ++j) zero.w[j] = 0u;
             *(V*)(col) = zero;
+            if constexpr (kSim) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    const uint64_t w = base + (uint64_t)(j * 64) + lane;
+                    if (w < W) L.sim_sig[w] = 0u;
+                }
+            }
             for (uint32_t i = 0; i < n; ++i) {
                 V x;
 #pragma unroll
-                for (int j = 0; j < K; ++j) x.w[j] = pi_word(i, base + (uint64_t)(j * 64) + lane);
+                for (int j = 0; j < K; ++j) {
+                    const uint64_t w = base + (uint64_t)(j * 64) + lane;
+                    if constexpr (kSim) {
+                        x.w[j] = w < W ? L.sim_pi[(size_t)i * W + w] : 0u;
+                        if (w < W) L.sim_sig[(size_t)(1 + i) * W + w] = x.w[j];
+                    } else {
+                        x.w[j] = pi_word(i, w);
+                    }
+                }
                 *(V*)(col + (size_t)(1 + i) * kRowWords) = x;
             }
             V m = zero;
@@ -140,13 +165,22 @@ __global__ void __launch_bounds__(1024) es_interp_kernel(InterpLaunch L) {
 #pragma unroll
                     for (int j = 0; j < K; ++j) r.w[j] = (a[u].w[j] ^ ca) & (b[u].w[j] ^ cb);
                     *(V*)(col + (size_t)ins[u].d * kRowWords) = r;
-                    if (ins[u].flags) {
+                    if constexpr (kSim) {
+                        if (ins[u].flags) {
+#pragma unroll
+                            for (int j = 0; j < K; ++j) {
+                                const uint64_t w = base + (uint64_t)(j * 64) + lane;
+                                if (w < W) L.sim_sig[(size_t)ins[u].flags * W + w] = r.w[j];
+                            }
+                        }
+                    } else if (ins[u].flags) {
                         const uint32_t op = 0u - (ins[u].flags & kOutPos), on = 0u - ((ins[u].flags >> 1) & 1u);
 #pragma unroll
                         for (int j = 0; j < K; ++j) m.w[j] |= (r.w[j] & op) | (~r.w[j] & on);
                     }
                 }
             }
+            if constexpr (kSim) continue;
             // Lowest failing pattern of this pass: first sub-word j with a nonzero lane, then
             // its lowest lane l, then the lowest set bit of that lane's word.
             uint64_t p = ~0ull;
@@ -167,21 +201,26 @@ __global__ void __launch_bounds__(1024) es_interp_kernel(InterpLaunch L) {
     }
 }
 
-template <int K, int B, bool kLds>
+template <int K, int B, bool kLds, bool kSim = false>
 hipError_t launch_one(const InterpLaunch& L, int grid, int block, hipStream_t stream) {
     const size_t lds = kLds ? interp_lds_bytes(L.rows_max, K, block / 64) : 0;
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&es_interp_kernel<K, B, kLds>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&es_interp_kernel<K, B, kLds, kSim>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((es_interp_kernel<K, B, kLds>), dim3(grid), dim3(block), lds, stream, L);
+    hipLaunchKernelGGL((es_interp_kernel<K, B, kLds, kSim>), dim3(grid), dim3(block), lds, stream, L);
     return hipGetLastError();
 }
 
 template <int K, int B>
 hipError_t launch_kb(const InterpLaunch& L, bool lds, int grid, int block, hipStream_t s) {
     return lds ? launch_one<K, B, true>(L, grid, block, s) : launch_one<K, B, false>(L, grid, block, s);
+}
+
+template <int K>
+hipError_t launch_sim_k(const InterpLaunch& L, bool lds, int grid, int block, hipStream_t s) {
+    return lds ? launch_one<K, 8, true, true>(L, grid, block, s) : launch_one<K, 8, false, true>(L, grid, block, s);
 }
 
 template <int K>
@@ -199,6 +238,16 @@ hipError_t launch_k(const InterpLaunch& L, int B, bool lds, int grid, int block,
 
 size_t interp_lds_bytes(uint32_t rows, int K, int waves_per_block) {
     return (size_t)waves_per_block * rows * 64u * (size_t)K * sizeof(uint32_t);
+}
+
+hipError_t launch_interp_sim(const InterpLaunch& L, int K, bool lds, int grid, int block, hipStream_t stream) {
+    if (L.num_cones != 1 || !L.sim_sig || grid <= 0 || block <= 0 || block % 64) return hipErrorInvalidValue;
+    switch (K) {
+        case 1: return launch_sim_k<1>(L, lds, grid, block, stream);
+        case 2: return launch_sim_k<2>(L, lds, grid, block, stream);
+        case 4: return launch_sim_k<4>(L, lds, grid, block, stream);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_interp(const InterpLaunch& L, int K, int B, bool lds, int grid, int block, hipStream_t stream) {

@@ -41,12 +41,27 @@ struct InterpLaunch {
     unsigned long long* best; // per cone: lowest failing pattern, ~0 = none yet
     uint32_t* hbm_rows;       // device value files (HBM tier); null for the LDS tier
     const int* cancel;        // device-visible flag polled per work item, may be null
+    // Simulation mode only (launch_interp_sim): the half-word index is a column of caller
+    // input words instead of a pattern range, and every gate's value is stored.
+    const uint32_t* sim_pi = nullptr;  // n rows of sim_words 32-bit words (row i = input i)
+    uint32_t* sim_sig = nullptr;       // rows 0..max_var of sim_words words (row v = variable v)
+    uint64_t sim_words = 0;
 };
 
 // Launch the interpreter.  K = half-words per lane per row (1, 2, 4); B = bundle size
 // (1, 4, 8, 16); lds = value file in LDS (else in hbm_rows).  Returns hipSuccess or an error.
 hipError_t launch_interp(const InterpLaunch& L, int K, int B, bool lds, int grid, int block,
                          hipStream_t stream);
+
+// Simulation mode of the interpreter: one cone, bundles of 8, instruction flags = the
+// variable a gate defines (0 = store nothing).  Columns [0, sim_words) are simulated once each.
+hipError_t launch_interp_sim(const InterpLaunch& L, int K, bool lds, int grid, int block, hipStream_t stream);
+
+// Per row of a signature matrix (rows x words, row-major): the number of ones and the
+// complement-normalised hash sum_k word'_k * (fmix32(k) | 1) mod 2^64, where word' is the
+// row complemented when its first bit is 1.  One wave per row, grid-stride over rows.
+hipError_t launch_signature_hash(const uint32_t* sig, uint64_t rows, uint64_t words, uint64_t* hash,
+                                 uint64_t* ones, int grid, hipStream_t stream);
 
 // Largest per-workgroup dynamic LDS the interpreter may request.
 size_t interp_lds_bytes(uint32_t rows, int K, int waves_per_block);

@@ -233,6 +233,14 @@ Plan make_plan(const Aig& g, Order order, uint32_t bundle) {
     }
     p.bundle = bundle;
     p.rows = g.num_inputs + p.peak_slots + 2;
+    // Gate instructions write a slot row and appear in the stream in evaluation order;
+    // padding and output-only steps write the sink row.
+    const uint32_t sink = g.num_inputs + 1 + p.peak_slots;
+    p.instr_gate.assign(p.prog.size(), UINT32_MAX);
+    size_t next = 0;
+    for (size_t t = 0; t < p.prog.size(); ++t)
+        if (p.prog[t].d != sink) p.instr_gate[t] = p.order[next++];
+    if (next != p.order.size()) throw Error{kErrInvalid, "planner: gate instructions do not match the order"};
     return p;
 }
 

@@ -47,6 +47,8 @@ struct Plan {
                               // that is not an AND's own value, no-ops padding the last bundle
     uint32_t num_gate_instrs = 0;  // instructions that are not padding
     std::vector<uint32_t> order;   // AND gates (index into the AIG) in evaluation order
+    std::vector<uint32_t> instr_gate;  // per prog entry: the AND gate it computes, or UINT32_MAX
+                                       // (output-only step or padding)
 };
 
 // bundle = 1: sequential stream.  bundle > 1: list-scheduled so that the gates of a

@@ -41,6 +41,14 @@ double now_ms() {
 // ---- circuits --------------------------------------------------------------
 
 Circuit::~Circuit() {
+    for (auto& kv : dev_sim_prog) {
+        if (!kv.second) continue;
+        int cur = 0;
+        if (hipGetDevice(&cur) == hipSuccess && hipSetDevice(kv.first) == hipSuccess) {
+            (void)hipFree(kv.second);
+            (void)hipSetDevice(cur);
+        }
+    }
     for (auto& kv : dev_prog) {
         if (!kv.second) continue;
         int cur = 0;
@@ -87,6 +95,41 @@ const Instr* Circuit::device_prog(int dev, uint32_t bundle, hipStream_t s) {
         FES_HIP(hipStreamSynchronize(s));
     }
     dev_prog[key] = d;
+    return d;
+}
+
+const Plan& Circuit::sim_plan() {
+    std::lock_guard<std::mutex> g(mu);
+    if (!sim) {
+        Aig all = aig;
+        std::vector<uint8_t> read(all.max_var() + 1, 0);
+        for (uint32_t k = 0; k < all.num_ands(); ++k) read[all.and_r0[k] >> 1] = read[all.and_r1[k] >> 1] = 1;
+        for (uint32_t o : all.outputs) read[o >> 1] = 1;
+        for (uint32_t k = 0; k < all.num_ands(); ++k)
+            if (!read[all.num_inputs + 1 + k]) all.outputs.push_back(2 * (all.num_inputs + 1 + k));
+        sim = std::make_unique<Plan>(make_plan(all, Order::Auto, 8));
+        if (sim->num_ands_tfi != aig.num_ands()) throw Error{kErrInvalid, "simulation plan misses gates"};
+        const std::string err = validate_plan(all, *sim);
+        if (!err.empty()) throw Error{kErrInvalid, "simulation plan: " + err};
+    }
+    return *sim;
+}
+
+const Instr* Circuit::device_sim_prog(int dev, hipStream_t s) {
+    const Plan& p = sim_plan();
+    std::lock_guard<std::mutex> g(mu);
+    auto it = dev_sim_prog.find(dev);
+    if (it != dev_sim_prog.end()) return it->second;
+    std::vector<Instr> prog = p.prog;
+    for (size_t t = 0; t < prog.size(); ++t)
+        prog[t].flags = p.instr_gate[t] == UINT32_MAX ? 0u : p.num_inputs + 1 + p.instr_gate[t];
+    Instr* d = nullptr;
+    FES_HIP(hipMalloc(&d, std::max<size_t>(prog.size(), 1) * sizeof(Instr)));
+    if (!prog.empty()) {
+        FES_HIP(hipMemcpyAsync(d, prog.data(), prog.size() * sizeof(Instr), hipMemcpyHostToDevice, s));
+        FES_HIP(hipStreamSynchronize(s));
+    }
+    dev_sim_prog[dev] = d;
     return d;
 }
 
@@ -178,12 +221,15 @@ int max_waves_per_cu(const Device&) { return 32; }
 }  // namespace
 
 bool make_schedule(Device& dev, const std::vector<Circuit*>& cs, int K, int B, int block, bool lds, Schedule& s) {
+    return make_schedule_rows(dev, rows_for(cs, B), K, B, block, lds, s);
+}
+
+bool make_schedule_rows(Device& dev, uint32_t rows, int K, int B, int block, bool lds, Schedule& s) {
     s = Schedule{};
     s.K = K;
     s.B = B;
     s.block = block;
     s.lds = lds;
-    const uint32_t rows = rows_for(cs, B);
     const size_t lds_cu = dev.prop.maxSharedMemoryPerMultiProcessor ? dev.prop.maxSharedMemoryPerMultiProcessor : 65536;
     const size_t lds_blk = dev.prop.sharedMemPerBlock ? dev.prop.sharedMemPerBlock : 65536;
     const int waves_per_block = block / 64;
@@ -322,6 +368,88 @@ void run_interp(Device& dev, const std::vector<Circuit*>& cs, const std::vector<
     FES_HIP(hipEventElapsedTime(&ms, e0, e1));
     if (kernel_ms) *kernel_ms = ms;
     best.assign(hbest, hbest + k);
+}
+
+}  // namespace fes
+
+namespace fes {
+
+void run_sim(Device& dev, Circuit& c, const uint32_t* pi, uint64_t words, uint32_t* sig,
+             const fastlec_es_options* o, hipStream_t stream, double* kernel_ms) {
+    const Plan& p = c.sim_plan();
+    // Schedule as a plain check would pick it (workgroup, then words per lane, shrink until a
+    // workgroup's value files fit in LDS; else value files in device memory), for this plan's rows.
+    int K = (o && o->words_per_thread) ? (int)o->words_per_thread : 2;
+    int block = (o && o->wg_size) ? (int)o->wg_size : 256;
+    bool lds = !(o && o->kernel == FASTLEC_KERNEL_INTERP_HBM);
+    if (K != 1 && K != 2 && K != 4) throw Error{kErrInvalid, "words_per_thread must be 1, 2 or 4"};
+    if (block < 64 || block > 1024 || block % 64) throw Error{kErrInvalid, "wg_size must be a multiple of 64 in [64, 1024]"};
+    Schedule sch;
+    while (lds && !make_schedule_rows(dev, p.rows, K, 8, block, true, sch)) {
+        if (!(o && o->wg_size) && block > 64) block /= 2;
+        else if (!(o && o->words_per_thread) && K > 1) K /= 2;
+        else lds = false;
+    }
+    if (!lds) make_schedule_rows(dev, p.rows, K, 8, block, false, sch);
+
+    const size_t waves = (size_t)sch.grid * (sch.block / 64);
+    const size_t file_bytes = sch.lds ? 0 : waves * p.rows * 64ull * sch.K * 4ull;
+    Layout lay = layout(1, file_bytes);
+    Buffer buf = dev.acquire(lay.total);
+    struct Releaser {
+        Device& d;
+        Buffer b;
+        ~Releaser() { d.release(b); }
+    } rel{dev, buf};
+    uint8_t* host = (uint8_t*)buf.host;
+    std::memset(host, 0, lay.files_off);
+    *(uint64_t*)(host + lay.best_off) = ~0ull;
+
+    ConeDesc& d = *(ConeDesc*)(host + lay.desc_off);
+    const uint32_t pass_hw = 64u * (uint32_t)sch.K;
+    d.prog = c.device_sim_prog(dev.ordinal, stream);
+    d.n_instr = (uint32_t)p.prog.size();
+    d.n_inputs = p.num_inputs;
+    d.rows = p.rows;
+    d.best_index = 0;
+    d.hw_begin = 0;
+    d.hw_end = words;
+    d.hw_first = 0;
+    uint64_t tile = o && o->tile_words ? 2ull * o->tile_words : 0;
+    if (!tile) {  // about 16 work items per wave, within [1, 64] passes
+        const uint64_t target = words / std::max<uint64_t>(1, waves * 16);
+        tile = pass_hw;
+        while (tile < target && tile < 64ull * pass_hw) tile *= 2;
+    }
+    d.tile_hw = (tile + pass_hw - 1) / pass_hw * pass_hw;
+    d.item_begin = 0;
+    d.item_end = (words + d.tile_hw - 1) / d.tile_hw;
+
+    uint8_t* devp = (uint8_t*)buf.dev;
+    InterpLaunch L;
+    L.cones = (const ConeDesc*)(devp + lay.desc_off);
+    L.num_cones = 1;
+    L.rows_max = p.rows;
+    L.total_items = d.item_end;
+    L.ctl = (LaunchCtl*)devp;
+    L.best = (unsigned long long*)(devp + lay.best_off);
+    L.hbm_rows = sch.lds ? nullptr : (uint32_t*)(devp + lay.files_off);
+    L.cancel = nullptr;
+    L.sim_pi = pi;
+    L.sim_sig = sig;
+    L.sim_words = words;
+
+    ScopedEvent e0, e1;
+    trace("sim launch: %llu words, %llu items, K=%d %s grid=%d block=%d rows=%u", (unsigned long long)words,
+          (unsigned long long)L.total_items, sch.K, sch.lds ? "lds" : "hbm", sch.grid, sch.block, p.rows);
+    FES_HIP(hipMemcpyAsync(devp, host, lay.files_off, hipMemcpyHostToDevice, stream));
+    FES_HIP(hipEventRecord(e0.e, stream));
+    FES_HIP(launch_interp_sim(L, sch.K, sch.lds, sch.grid, sch.block, stream));
+    FES_HIP(hipEventRecord(e1.e, stream));
+    FES_HIP(hipStreamSynchronize(stream));
+    float ms = 0;
+    FES_HIP(hipEventElapsedTime(&ms, e0.e, e1.e));
+    if (kernel_ms) *kernel_ms = ms;
 }
 
 }  // namespace fes

@@ -65,10 +65,16 @@ struct Circuit {
     std::map<std::pair<int, uint32_t>, Instr*> dev_prog;                  // (device, bundle) -> stream
     std::map<int, std::shared_ptr<JitKernel>> jit;                       // waves_per_eu -> kernel
     std::unique_ptr<LutProgram> lut;                                      // specialized-kernel program
+    std::unique_ptr<Plan> sim;                                            // random-simulation plan
+    std::map<int, Instr*> dev_sim_prog;                                   // device -> its stream
     ~Circuit();
     const LutProgram& lut_program();
     const Plan& plan_for(uint32_t bundle);
     const Instr* device_prog(int device, uint32_t bundle, hipStream_t s);
+    // Simulation covers every AND gate: the plan is made for the outputs plus every gate
+    // that feeds nothing, in bundles of 8; each gate instruction's flags hold its variable.
+    const Plan& sim_plan();
+    const Instr* device_sim_prog(int device, hipStream_t s);
 };
 
 // Device buffers handed out per call (thread-safe pool).
@@ -129,6 +135,12 @@ Schedule default_schedule(Device& dev, const std::vector<Circuit*>& cs, const fa
 // Schedule for fixed K (half-words per lane), B (bundle) and workgroup size; lds = prefer LDS
 // value files.  Returns false when that combination does not fit (LDS too small).
 bool make_schedule(Device& dev, const std::vector<Circuit*>& cs, int K, int B, int block, bool lds, Schedule& out);
+bool make_schedule_rows(Device& dev, uint32_t rows, int K, int B, int block, bool lds, Schedule& out);
+
+// Random-pattern simulation: value of every variable on `words` columns of input words
+// (pi: n rows, sig: max_var + 1 rows, both row-major on the device).
+void run_sim(Device& dev, Circuit& c, const uint32_t* pi, uint64_t words, uint32_t* sig,
+             const fastlec_es_options* o, hipStream_t stream, double* kernel_ms);
 // Fastest interpreter schedule for this set of cones, measured on a bounded prefix of each
 // cone's range and cached per device and batch shape.
 Schedule autotune(Device& dev, const std::vector<Circuit*>& cs, const std::vector<HwRange>& ranges, hipStream_t stream,

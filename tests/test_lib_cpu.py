@@ -137,3 +137,24 @@ def test_specialized_kernel_compiles_for_gfx950():
     assert info["code_bytes"] > 1000
     src = es.fastlec_es_specialized_source(c, 2)
     assert "fes_es_kernel" in src and "v_bitop3_b32" in src
+
+
+def test_classes_match_oracle_on_host():
+    """fastlec_es_classes runs on the host: first row of each hash value, as the oracle."""
+    from oracle import rsim
+    r = np.random.default_rng(4)
+    for rows in (0, 1, 7, 5000):
+        h = r.integers(0, 40, size=rows, dtype=np.uint64) * np.uint64(0x9E3779B97F4A7C15)
+        assert np.array_equal(es.fastlec_es_classes(h), rsim.classes(h))
+
+
+def test_simulation_argument_errors_without_gpu():
+    from miters.miter import mult_circuit
+    c = es.fastlec_es_load_aig(mult_circuit("array", 3).to_aig())
+    for call in (lambda: es.fastlec_es_simulate(c, 1, 0, 1),          # no words
+                 lambda: es.fastlec_es_simulate(c, None, 4, 1),       # inputs needed
+                 lambda: es.fastlec_es_signature_hash(0, 1, 1, 1, 1),  # null signature
+                 lambda: es.fastlec_es_signature_hash(1, 0, 1, 1, 1)):  # no rows
+        with pytest.raises(es.EsError) as ei:
+            call()
+        assert ei.value.code == -5
