@@ -170,6 +170,47 @@ def rsim_leg(es, stream, workload: str = "mult16_array_booth", words: int = 1 <<
             "rows_in_such_classes": int(sizes[sizes >= 2].sum())}
 
 
+def sweep_leg(es, stream, workload: str = "mult12_array_booth", words: int = 1 << 12):
+    """One virtual sweeping pass (paper, Sections 2.3 and 3.2): simulate seeded random words,
+    hash, group candidate classes, cut out every candidate pair's sub-miter and check them all
+    with one batched exact-simulation call.  Times each stage; returns verdict counts."""
+    import numpy as np
+    import torch
+    import miters
+    g = miters.workload(workload)
+    c = es.fastlec_es_load_aig(g.to_aig())
+    info = c.info()
+    n, V = info["num_pis"], info["num_pis"] + info["num_ands"]
+    rng = np.random.default_rng(9)
+    pi = torch.from_numpy(rng.integers(0, 1 << 32, size=(n, words), dtype=np.uint64).astype(np.uint32)
+                          .view(np.int32)).cuda()
+    sig = torch.empty((V + 1, words), dtype=torch.int32, device="cuda")
+    h = torch.empty(V + 1, dtype=torch.int64, device="cuda")
+    ones = torch.empty(V + 1, dtype=torch.int64, device="cuda")
+    t = {}
+    t0 = time.perf_counter()
+    es.fastlec_es_simulate(c, pi, words, sig, stream=stream)
+    es.fastlec_es_signature_hash(sig, V + 1, words, h, ones, stream=stream)
+    hh = h.cpu().numpy().view(np.uint64)
+    pol = (sig[:, 0] & 1).to(torch.uint8).cpu().numpy()
+    t["simulate_hash_s"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    cls = es.fastlec_es_classes(hh)
+    targets = [v for v in range(n + 1, V + 1) if cls[v] != v]
+    subs = [es.fastlec_es_submiter_aag(c, cls, pol, v)[0] for v in targets]
+    circuits = [es.fastlec_es_load_aig(text) for text in subs]
+    t["classes_extract_load_s"] = time.perf_counter() - t0
+    work = sum(x.info()["num_ands_tfi"] * (1 << x.info()["num_pis"]) for x in circuits)
+    t0 = time.perf_counter()
+    res = es.fastlec_es_check_batch(circuits, stream=stream)
+    t["batch_check_s"] = time.perf_counter() - t0
+    eq = sum(r["verdict"] == es.FASTLEC_EQUIVALENT for r in res)
+    return {"workload": workload, "words": words, "patterns": 32 * words, "targets": len(targets),
+            "equivalent": eq, "nonequivalent": len(targets) - eq, "submiter_node_patterns": work,
+            "batch_node_patterns_per_s": work / t["batch_check_s"], **t,
+            "total_s": sum(t.values())}
+
+
 def serve_leg(es, stream, seed: int = 5, seconds: float = 30.0, max_requests: int = 400,
               pool: int = 40, budget_gib: int = 64, load: float = 0.7):
     """Poisson stream of cones (n ~ U{16..34}, ~U[500, 20000] AND gates, 10% faulty) served by
@@ -344,6 +385,8 @@ def main():
         print(json.dumps({"progress": "batch_small", **sec["batch_small"]}), file=sys.stderr, flush=True)
         sec["rsim"] = rsim_leg(es, stream)
         print(json.dumps({"progress": "rsim", **sec["rsim"]}), file=sys.stderr, flush=True)
+        sec["sweep"] = sweep_leg(es, stream)
+        print(json.dumps({"progress": "sweep", **sec["sweep"]}), file=sys.stderr, flush=True)
         sec["serve"] = serve_leg(es, stream, seconds=a.serve_seconds)
         out["secondary"] = sec
     print(json.dumps(out), flush=True)

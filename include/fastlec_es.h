@@ -214,6 +214,38 @@ int fastlec_es_signature_hash(const uint32_t *sig, uint64_t rows, uint64_t num_w
                               const fastlec_es_options *opts, double *kernel_ms);
 int fastlec_es_classes(const uint64_t *hash, uint64_t rows, uint32_t *class_of);
 
+/* ---- sub-miters by virtual sweeping (host only) ----------------------------- */
+
+/* The paper's scheduling units: imitate one sweeping pass without proving anything.  Each
+ * candidate pair keeps only the fan-in cones of its two nodes, and every earlier candidate is
+ * merged into its class representative as if already proven (paper, Section 3.2, data
+ * features preparation; the sweeping flow of Section 2.3).
+ *
+ * class_of  host, rows = max_var + 1 entries: representative of each variable (the lowest
+ *           member of its class, class_of[u] <= u), as fastlec_es_classes returns.
+ * polarity  host, rows entries: bit 0 of word 0 of each variable's signature row (its value
+ *           at the first simulated pattern).  u and class_of[u] are candidates for equality
+ *           when their polarities agree and for complement when they differ.
+ * target    an AND variable with class_of[target] < target.
+ * Rules: a literal 2u + c of a non-representative AND u is read as 2 class_of[u] +
+ * (c ^ polarity[u] ^ polarity[class_of[u]]); target's own gate is kept with its fan-ins read
+ * so; the kept gates are those reachable from target's read fan-ins and from its
+ * representative r; the output is XOR(target, r ^ (polarity[target] ^ polarity[r])), as
+ * three AND gates t1 = a & b, t2 = ~a & ~b, out = ~t1 & ~t2.  It is constant 0 iff the
+ * pair is equivalent under the merges.
+ * Text: ASCII AIGER, no symbols.  Inputs = the original inputs in the support, ascending,
+ * as variables 1..k; then the kept gates in ascending original order (operands in the
+ * original order); then t1, t2, out.
+ * buf/len   the text, NUL-terminated; *needed (may be NULL) = bytes it needs with the NUL.
+ *           buf may be NULL to ask for the size; a short buf gets FASTLEC_ERR_INVALID.
+ * inputs    may be NULL; else at least num_pis entries: original index of each sub-miter
+ *           input.  *num_inputs (may be NULL) = k.
+ * FASTLEC_ERR_INVALID for a wrong rows count, a target that is not a non-representative
+ * AND, a representative above its member, or a polarity entry other than 0 and 1. */
+int fastlec_es_submiter_aag(const fastlec_es_circuit *c, const uint32_t *class_of, const uint8_t *polarity,
+                            uint64_t rows, uint32_t target, char *buf, size_t len, size_t *needed,
+                            uint32_t *inputs, uint32_t *num_inputs);
+
 /* ---- diagnostics (no GPU needed) ------------------------------------------ */
 
 /* Compile the specialized kernel of c for gfx950 with hipRTC (cached per circuit and by

@@ -111,6 +111,10 @@ SIGNATURES = [
                                                  ctypes.POINTER(fastlec_es_options), ctypes.POINTER(ctypes.c_double)]),
     ("fastlec_es_classes", ctypes.c_int, [ctypes.POINTER(ctypes.c_uint64), ctypes.c_uint64,
                                           ctypes.POINTER(ctypes.c_uint32)]),
+    ("fastlec_es_submiter_aag", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint8),
+                                               ctypes.c_uint64, ctypes.c_uint32, ctypes.c_char_p, ctypes.c_size_t,
+                                               ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_uint32),
+                                               ctypes.POINTER(ctypes.c_uint32)]),
 ]
 
 _lib = None
@@ -303,6 +307,31 @@ def fastlec_es_classes(hashes):
     if rc:
         _raise(rc)
     return out
+
+
+def fastlec_es_submiter_aag(circuit: Circuit, class_of, polarity, target: int):
+    """(ASCII AIGER bytes of the sub-miter of pair (target, class_of[target]), original input
+    index of each of its inputs).  class_of, polarity: host arrays of max_var + 1 entries."""
+    import numpy as np
+    cls = np.ascontiguousarray(np.asarray(class_of, dtype=np.uint32))
+    pol = np.ascontiguousarray(np.asarray(polarity, dtype=np.uint8))
+    if cls.size != pol.size:
+        raise ValueError("class_of and polarity must have the same length")
+    L = lib()
+    cp = cls.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+    pp = pol.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    need = ctypes.c_size_t()
+    k = ctypes.c_uint32()
+    rc = L.fastlec_es_submiter_aag(circuit.handle, cp, pp, cls.size, target, None, 0, ctypes.byref(need), None,
+                                   ctypes.byref(k))
+    if rc:
+        _raise(rc)
+    buf = ctypes.create_string_buffer(need.value)
+    ins = (ctypes.c_uint32 * max(1, circuit.info()["num_pis"]))()
+    rc = L.fastlec_es_submiter_aag(circuit.handle, cp, pp, cls.size, target, buf, need.value, None, ins, None)
+    if rc:
+        _raise(rc)
+    return buf.value, list(ins[:k.value])
 
 
 class Server:

@@ -385,4 +385,22 @@ int fastlec_es_classes(const uint64_t* hash, uint64_t rows, uint32_t* class_of) 
     });
 }
 
+int fastlec_es_submiter_aag(const fastlec_es_circuit* c, const uint32_t* class_of, const uint8_t* polarity,
+                            uint64_t rows, uint32_t target, char* buf, size_t len, size_t* needed,
+                            uint32_t* inputs, uint32_t* num_inputs) {
+    return guarded([&] {
+        if (!c || !class_of || !polarity) throw Error{kErrInvalid, "null argument"};
+        std::vector<uint32_t> ins;
+        const std::string text = submiter_aag(c->c.aig, class_of, polarity, rows, target, &ins);
+        if (needed) *needed = text.size() + 1;
+        if (num_inputs) *num_inputs = (uint32_t)ins.size();
+        if (inputs) std::copy(ins.begin(), ins.end(), inputs);
+        if (buf) {
+            if (len < text.size() + 1) throw Error{kErrInvalid, "buffer too small"};
+            std::memcpy(buf, text.c_str(), text.size() + 1);
+        }
+        return FASTLEC_OK;
+    });
+}
+
 }  // extern "C"

@@ -137,6 +137,11 @@ Schedule default_schedule(Device& dev, const std::vector<Circuit*>& cs, const fa
 bool make_schedule(Device& dev, const std::vector<Circuit*>& cs, int K, int B, int block, bool lds, Schedule& out);
 bool make_schedule_rows(Device& dev, uint32_t rows, int K, int B, int block, bool lds, Schedule& out);
 
+// Sub-miter of candidate pair (target, class_of[target]) by virtual sweeping, as ASCII AIGER;
+// inputs (if not null) receives the original input index of each sub-miter input.
+std::string submiter_aag(const Aig& g, const uint32_t* class_of, const uint8_t* polarity, uint64_t rows,
+                         uint32_t target, std::vector<uint32_t>* inputs);
+
 // Random-pattern simulation: value of every variable on `words` columns of input words
 // (pi: n rows, sig: max_var + 1 rows, both row-major on the device).
 void run_sim(Device& dev, Circuit& c, const uint32_t* pi, uint64_t words, uint32_t* sig,
