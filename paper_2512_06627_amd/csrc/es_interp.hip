@@ -89,8 +89,16 @@ __global__ void __launch_bounds__(1024) es_interp_kernel(InterpLaunch L) {
     // Control flow stays wave-uniform: every lane takes part in the claim (lane 0 adds 1,
     // the others 0) and in the atomicMin (all lanes hold the same value), so no branch
     // depends on the lane and every loop exit is a scalar branch.
+    const uint32_t wave_gid = blockIdx.x * (blockDim.x >> 6) + wave;
+    // A grid with fewer waves than counters uses one counter per wave, so every counter in
+    // use has a wave and every item is claimed.
+    const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+    const uint32_t nclaim = waves < kClaimCounters ? waves : kClaimCounters;
+    const uint32_t claim = __builtin_amdgcn_readfirstlane(wave_gid % nclaim);  // wave-uniform
+    unsigned long long* const counter = &L.ctl->next_item[claim * kClaimStride];
     for (;;) {
-        const uint64_t item = uniform64(atomicAdd(&L.ctl->next_item, lane == 0 ? 1ull : 0ull));
+        const uint64_t k = uniform64(atomicAdd(counter, lane == 0 ? 1ull : 0ull));
+        const uint64_t item = claim + k * nclaim;
         if (item >= L.total_items) break;
         if (L.cancel && __builtin_amdgcn_readfirstlane(
                             __hip_atomic_load(L.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)))

@@ -107,10 +107,19 @@ std::string jit_source(const LutProgram& lp, int waves_per_eu, int block, int* w
     // Control flow stays wave-uniform: every lane takes part in the claim (lane 0 adds 1, the
     // others 0) and in the atomicMin (all lanes hold the same value), so no branch depends on
     // the lane and every loop exit is a scalar branch.
-    o << "  for (;;) {\n"
-         "    const u64 claimed = atomicAdd(next_item, lane == 0u ? 1ull : 0ull);\n"
-         "    const u64 item = ((u64)__builtin_amdgcn_readfirstlane((u32)(claimed >> 32)) << 32) |\n"
-         "                     __builtin_amdgcn_readfirstlane((u32)claimed);\n"
+    // Claims are spread over several counters on separate 128-byte lines (counter s hands out
+    // items s, s + C, s + 2C, ...), so short work items are not serialised at one atomic.
+    // A grid with fewer waves than counters uses one counter per wave, so every counter in use
+    // has a wave and every item is claimed.
+    o << "  const u32 waves = gridDim.x * (blockDim.x >> 6);\n"
+         "  const u32 nclaim = waves < " << kClaimCounters << "u ? waves : " << kClaimCounters << "u;\n"
+         "  const u32 claim = __builtin_amdgcn_readfirstlane((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % nclaim);\n"
+         "  u64* const counter = next_item + claim * " << kClaimStride << "u;\n"
+         "  for (;;) {\n"
+         "    const u64 claimed = atomicAdd(counter, lane == 0u ? 1ull : 0ull);\n"
+         "    const u64 k = ((u64)__builtin_amdgcn_readfirstlane((u32)(claimed >> 32)) << 32) |\n"
+         "                  __builtin_amdgcn_readfirstlane((u32)claimed);\n"
+         "    const u64 item = claim + k * nclaim;\n"
          "    if (item >= total_items) break;\n"
          "    if (cancel && __builtin_amdgcn_readfirstlane(__hip_atomic_load(cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))) break;\n"
          "    const u64 hw0 = hw_first + item * tile_hw;\n"
@@ -437,12 +446,14 @@ void run_jit(Device& dev, Circuit& c, JitKernel& k, const HwRange& r, uint64_t t
         Buffer b;
         ~Releaser() { d.release(b); }
     } rel{dev, buf};
+    static_assert(kClaimBytes + 8 <= 4096, "claim counters and best fit the buffer");
     uint64_t* host = (uint64_t*)buf.host;
-    std::memset(host, 0, 128);
-    host[8] = ~0ull;  // best at byte offset 64, the counter at 0
+    std::memset(host, 0, kClaimBytes);
+    uint64_t* hbest = host + kClaimBytes / 8;
+    *hbest = ~0ull;  // the claim counters at 0, best right after them
     uint8_t* devp = (uint8_t*)buf.dev;
     uint64_t* next_item = (uint64_t*)devp;
-    uint64_t* best = (uint64_t*)(devp + 64);
+    uint64_t* best = (uint64_t*)(devp + kClaimBytes);
     hipEvent_t e0, e1;
     FES_HIP(hipEventCreate(&e0));
     FES_HIP(hipEventCreate(&e1));
@@ -453,17 +464,17 @@ void run_jit(Device& dev, Circuit& c, JitKernel& k, const HwRange& r, uint64_t t
             (void)hipEventDestroy(b);
         }
     } ev{e0, e1};
-    FES_HIP(hipMemcpyAsync(devp, host, 128, hipMemcpyHostToDevice, stream));
+    FES_HIP(hipMemcpyAsync(devp, host, kClaimBytes + 8, hipMemcpyHostToDevice, stream));
     FES_HIP(hipEventRecord(e0, stream));
     jit_enqueue(lp, next_item, best, cancel, stream);
     FES_HIP(hipEventRecord(e1, stream));
-    FES_HIP(hipMemcpyAsync(host + 8, best, 8, hipMemcpyDeviceToHost, stream));
+    FES_HIP(hipMemcpyAsync(hbest, best, 8, hipMemcpyDeviceToHost, stream));
     FES_HIP(hipStreamSynchronize(stream));
     trace("specialized done");
     float ms = 0;
     FES_HIP(hipEventElapsedTime(&ms, e0, e1));
     if (kernel_ms) *kernel_ms = ms;
-    *best_out = host[8];
+    *best_out = *hbest;
 }
 
 }  // namespace fes

@@ -26,11 +26,21 @@ struct ConeDesc {
 };
 static_assert(sizeof(ConeDesc) == 72, "descriptor layout");
 
-// Control block at the start of each launch's device buffer.
-struct alignas(64) LaunchCtl {
-    unsigned long long next_item;  // work-claim counter
-    unsigned long long pad[7];
+// Work claims are spread over C = min(kClaimCounters, waves in the grid) counters, each on
+// its own 128-byte line: the wave with global index w claims from counter s = w % C and gets
+// the items s, s + C, s + 2C, ... in that order.  One shared counter
+// serialises every claim of the launch at the atomic unit (about 30 ns each), which bounds
+// launches of many short work items; spread over separate lines the claims proceed in
+// parallel, and the items still start in roughly ascending order.
+constexpr uint32_t kClaimCounters = 16;
+constexpr uint32_t kClaimStride = 16;  // 64-bit words from one counter to the next (128 bytes)
+constexpr size_t kClaimBytes = sizeof(unsigned long long) * kClaimCounters * kClaimStride;
+
+// Control block at the start of each launch's device buffer (all zero before a launch).
+struct alignas(128) LaunchCtl {
+    unsigned long long next_item[kClaimCounters * kClaimStride];  // claim counters, see above
 };
+static_assert(sizeof(LaunchCtl) == kClaimBytes, "control block layout");
 
 struct InterpLaunch {
     const ConeDesc* cones;

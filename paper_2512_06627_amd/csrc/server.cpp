@@ -85,7 +85,7 @@ struct fastlec_es_server {
 
     // device job table: [ctl lds][ctl hbm][best x capacity][desc lds x capacity][desc hbm x capacity]
     Buffer table;
-    size_t off_best = 128, off_desc_lds = 0, off_desc_hbm = 0;
+    size_t off_best = 2 * sizeof(LaunchCtl), off_desc_lds = 0, off_desc_hbm = 0;
     Buffer files;  // value files of the device-memory tier
     std::vector<uint32_t> free_slots;
     double rate = 1e14;  // node*patterns per second, running estimate
@@ -228,7 +228,7 @@ void fastlec_es_server::step(const std::vector<Job*>& act) {
     }
     uint8_t* host = (uint8_t*)table.host;
     uint8_t* devp = (uint8_t*)table.dev;
-    std::memset(host, 0, 128);
+    std::memset(host, 0, 2 * sizeof(LaunchCtl));
     struct Group {
         std::vector<Circuit*>* c;
         std::vector<HwRange>* r;
@@ -238,7 +238,7 @@ void fastlec_es_server::step(const std::vector<Job*>& act) {
         Schedule sch;
         uint64_t items = 0;
     };
-    Group groups[2] = {{&lds_c, &lds_r, &lds_i, 0, off_desc_lds, true, {}}, {&hbm_c, &hbm_r, &hbm_i, 64, off_desc_hbm, false, {}}};
+    Group groups[2] = {{&lds_c, &lds_r, &lds_i, 0, off_desc_lds, true, {}}, {&hbm_c, &hbm_r, &hbm_i, sizeof(LaunchCtl), off_desc_hbm, false, {}}};
     for (Group& g : groups) {
         if (g.c->empty()) continue;
         fastlec_es_options o = opts;
@@ -257,7 +257,7 @@ void fastlec_es_server::step(const std::vector<Job*>& act) {
         }
     }
     // Upload the control words and this step's descriptors (best[] stays on the device).
-    FES_HIP(hipMemcpyAsync(devp, host, 128, hipMemcpyHostToDevice, stream));
+    FES_HIP(hipMemcpyAsync(devp, host, 2 * sizeof(LaunchCtl), hipMemcpyHostToDevice, stream));
     for (Group& g : groups)
         if (!g.c->empty())
             FES_HIP(hipMemcpyAsync(devp + g.desc_off, host + g.desc_off, sizeof(ConeDesc) * g.c->size(),
@@ -281,14 +281,13 @@ void fastlec_es_server::step(const std::vector<Job*>& act) {
     // Specialized slices: own claim counter per slot (zeroed first), shared best[] entry.
     double jit_np = 0;
     if (!jit_jobs.empty()) {
-        uint64_t* hc = (uint64_t*)(host + off_ctl_jit);
         for (size_t t : jit_jobs) {
             Job* j = act[t];
-            hc[j->slot] = 0;
-            FES_HIP(hipMemcpyAsync(devp + off_ctl_jit + 8ull * j->slot, &hc[j->slot], 8, hipMemcpyHostToDevice, stream));
+            const size_t off = off_ctl_jit + kClaimBytes * j->slot;
+            std::memset(host + off, 0, kClaimBytes);
+            FES_HIP(hipMemcpyAsync(devp + off, host + off, kClaimBytes, hipMemcpyHostToDevice, stream));
             const JitLaunchPlan lp = jit_prepare(*dev, *jk[t], windows[t], 0);
-            jit_enqueue(lp, (uint64_t*)(devp + off_ctl_jit + 8ull * j->slot), (uint64_t*)(devp + off_best + 8ull * j->slot),
-                        nullptr, stream);
+            jit_enqueue(lp, (uint64_t*)(devp + off), (uint64_t*)(devp + off_best + 8ull * j->slot), nullptr, stream);
             jit_np += 32.0 * std::max<uint32_t>(1, j->c->plan1.num_gate_instrs) * (double)(windows[t].end - windows[t].begin);
         }
         FES_HIP(hipEventRecord(e2.e, stream));
@@ -428,7 +427,7 @@ int fastlec_es_server_create(const fastlec_es_options* opts, size_t budget_bytes
         s->off_desc_lds = (s->off_best + 8ull * kCapacity + 255) & ~size_t(255);
         s->off_desc_hbm = s->off_desc_lds + sizeof(ConeDesc) * kCapacity;
         s->off_ctl_jit = (s->off_desc_hbm + sizeof(ConeDesc) * kCapacity + 255) & ~size_t(255);
-        s->table = s->dev->acquire(s->off_ctl_jit + 8ull * kCapacity);
+        s->table = s->dev->acquire(s->off_ctl_jit + kClaimBytes * kCapacity);
         for (uint32_t i = kCapacity; i-- > 0;) s->free_slots.push_back(i);
         s->st.budget_bytes = budget_bytes;
         fastlec_es_server* raw = s.get();
