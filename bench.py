@@ -35,8 +35,8 @@ PEAK_HBM = 8.0e12                                        # bytes/s, MI355X HBM3E
 # WRITE_SIZE (each scaled by what the counter reads for a device copy of known size; summary
 # and commands in profiles/es_specialized_mult16_counters.md).  Valid only for the kernel whose
 # generated source has this SHA-256; any other kernel reports null.
-PROFILED_TRAFFIC = {"source_sha256": "9fae5f35b5a1ef213fec8f5f551f4b63918c0ec8fc30876f31e7d763a86db6ed",
-                    "bytes_per_launch": 2944953}
+PROFILED_TRAFFIC = {"source_sha256": "ccfed8e35eb6ab3f4566538fd3ce89de8cf2566bf0f9ba1c2d1a3c6eb9a9df06",
+                    "bytes_per_launch": 1372081}
 
 
 def profiled_traffic(es, c):

@@ -121,11 +121,14 @@ int fastlec_es_info_get(const fastlec_es_circuit *c, fastlec_es_info *info);
 int fastlec_es_check(const fastlec_es_circuit *c, const fastlec_es_options *opts, fastlec_es_result *out);
 
 /* Exact simulation of k circuits of different sizes and input counts (whole space each; the
- * option's word range is ignored).  Circuits are grouped by value-file size (powers of two of
- * the row count); each group is one persistent interpreter launch over all its cones, in
- * longest-processing-time order, with a tuned schedule (or the option's schedule fields) and
- * recorded once as a hipGraph.  cs: k handles; out: k results.  Returns the first
- * per-circuit error; per-circuit errors also appear as a negative verdict. */
+ * option's word range is ignored).  With kernel AUTO, circuits that the runtime model
+ * (fastlec_es_predict) gives to the specialized kernel are compiled in parallel host threads
+ * and run as their own launches (kernel_ms and compile_ms their own).  The others are grouped
+ * by value-file size (powers of two of the row count); each group is one persistent
+ * interpreter launch over all its cones, in longest-processing-time order, with a tuned
+ * schedule (or the option's schedule fields) and recorded once as a hipGraph; their kernel_ms
+ * is the sum over the groups.  cs: k handles; out: k results.  Returns the first per-circuit
+ * error; per-circuit errors also appear as a negative verdict. */
 int fastlec_es_check_batch(const fastlec_es_circuit *const *cs, size_t k, const fastlec_es_options *opts,
                            fastlec_es_result *out);
 
@@ -245,6 +248,20 @@ int fastlec_es_classes(const uint64_t *hash, uint64_t rows, uint32_t *class_of);
 int fastlec_es_submiter_aag(const fastlec_es_circuit *c, const uint32_t *class_of, const uint8_t *polarity,
                             uint64_t rows, uint32_t target, char *buf, size_t len, size_t *needed,
                             uint32_t *inputs, uint32_t *num_inputs);
+
+/* ---- runtime model (host only) -------------------------------------------- */
+
+/* Predicted kernel times of a plain check of c over [begin_word, end_word) (0, 0 = the whole
+ * space), by the paper's runtime form (linear in gates, exponential in inputs; Section 3.2,
+ * runtime prediction) fitted per kernel on MI355X with a fixed launch cost:
+ *   interp_ms       t0 + N * max(patterns / R, L); R depends on the value-file size (S)
+ *   specialized_ms  t0 + (LUT steps) * max(1, patterns / 2048) / R
+ *   compile_ms      hipRTC compile of the specialized kernel: c0 + c1 * (LUT steps)
+ * Median errors on the fitting set: 8%, 16%, 1%.  Outputs may be NULL; asking for
+ * specialized_ms or compile_ms builds the circuit's LUT program (host time).  The AUTO kernel
+ * choice of fastlec_es_check uses the same model. */
+int fastlec_es_predict(const fastlec_es_circuit *c, uint64_t begin_word, uint64_t end_word, double *interp_ms,
+                       double *specialized_ms, double *compile_ms);
 
 /* ---- diagnostics (no GPU needed) ------------------------------------------ */
 

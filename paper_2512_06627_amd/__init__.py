@@ -111,6 +111,8 @@ SIGNATURES = [
                                                  ctypes.POINTER(fastlec_es_options), ctypes.POINTER(ctypes.c_double)]),
     ("fastlec_es_classes", ctypes.c_int, [ctypes.POINTER(ctypes.c_uint64), ctypes.c_uint64,
                                           ctypes.POINTER(ctypes.c_uint32)]),
+    ("fastlec_es_predict", ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     ("fastlec_es_submiter_aag", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint8),
                                                ctypes.c_uint64, ctypes.c_uint32, ctypes.c_char_p, ctypes.c_size_t,
                                                ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_uint32),
@@ -307,6 +309,16 @@ def fastlec_es_classes(hashes):
     if rc:
         _raise(rc)
     return out
+
+
+def fastlec_es_predict(circuit: Circuit, begin_word: int = 0, end_word: int = 0) -> dict:
+    """Predicted kernel times (ms) of a plain check: interpreter, specialized kernel, compile."""
+    i, s, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    rc = lib().fastlec_es_predict(circuit.handle, begin_word, end_word, ctypes.byref(i), ctypes.byref(s),
+                                  ctypes.byref(c))
+    if rc:
+        _raise(rc)
+    return {"interp_ms": i.value, "specialized_ms": s.value, "compile_ms": c.value}
 
 
 def fastlec_es_submiter_aag(circuit: Circuit, class_of, polarity, target: int):

@@ -8,6 +8,7 @@
 #include <unordered_map>
 #include <fstream>
 #include <sstream>
+#include <thread>
 
 #include "runtime.hpp"
 
@@ -68,17 +69,23 @@ void fill_result(const Circuit& c, const HwRange& r, uint64_t best, fastlec_es_r
     }
 }
 
-// Choose the kernel: the specialized one pays a hipRTC compile once per circuit (about 0.2 s
-// plus 0.03 ms per gate), so without a compiled kernel it is used when the interpreter
-// (about 3e13 node*patterns/s) would take more than twice that; a compiled kernel is used
-// for any space beyond a launch's worth.
+// Choose the kernel by the runtime model: a compiled specialized kernel when it is predicted
+// faster; otherwise the specialized kernel only when its time plus the hipRTC compile, with a
+// safety margin of 1.5 on the compile (the paper's margin against prediction error in its
+// engine rules, Section 3.2), beats the interpreter.  The LUT program (needed for the
+// specialized prediction) is only built when the interpreter's time could pay for a compile.
+constexpr double kCompileMargin = 1.5;
+
 bool use_specialized(Circuit& c, const fastlec_es_options& o, const HwRange& r) {
     if (o.kernel == FASTLEC_KERNEL_SPECIALIZED) return true;
     if (o.kernel != FASTLEC_KERNEL_AUTO) return false;
-    const double gates = std::max<uint32_t>(1, c.plan1.num_gate_instrs);
-    const double work = gates * 32.0 * (double)(r.end - r.begin);
-    if (jit_ready(c, specialized_waves_per_eu())) return work >= 1e11;
-    return work >= 3e13 * 2.0 * (0.2 + 3e-5 * gates);
+    const double patterns = 32.0 * (double)(r.end - r.begin);
+    const double t_interp = model_interp_ms(std::max<uint32_t>(1, c.plan1.num_gate_instrs), c.plan1.peak_slots, patterns);
+    if (jit_ready(c, specialized_waves_per_eu()))
+        return model_specialized_ms(c.lut_program().lut_steps, patterns) < t_interp;
+    if (t_interp < kCompileMargin * model_compile_ms(0)) return false;
+    const uint32_t luts = c.lut_program().lut_steps;
+    return model_specialized_ms(luts, patterns) + kCompileMargin * model_compile_ms(luts) < t_interp;
 }
 
 void check_one(Circuit& c, const fastlec_es_options& o, fastlec_es_result* out) {
@@ -219,12 +226,24 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
             v.push_back(const_cast<Circuit*>(&cs[i]->c));
             rs.push_back(range_of(v.back()->plan1.num_inputs, 0, 0));
         }
+        // Cones the runtime model gives to the specialized kernel (AUTO only) are compiled in
+        // parallel host threads and run as their own launches; the rest share interpreter
+        // launches.
+        std::vector<size_t> spec;
+        std::vector<uint8_t> is_spec(k, 0);
+        if (o.kernel == FASTLEC_KERNEL_AUTO)
+            for (size_t i = 0; i < k; ++i)
+                if (use_specialized(*v[i], o, rs[i])) {
+                    is_spec[i] = 1;
+                    spec.push_back(i);
+                }
         // Groups by value-file size: one launch sizes every wave's file for its largest cone,
         // so cones with few rows would otherwise run at the occupancy of the largest.  Rows
         // are bucketed by powers of two; each group gets its own schedule and recorded launch,
         // and the groups run back to back on the stream.
         std::map<uint32_t, std::vector<size_t>> groups;
         for (size_t i = 0; i < k; ++i) {
+            if (is_spec[i]) continue;
             uint32_t rows = v[i]->plan_for(8).rows, b = 0;
             while (rows > 1) {
                 rows >>= 1;
@@ -255,7 +274,41 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
                 fill_result(*v[i], rs[i], best[t], &out[i]);
             }
         }
-        for (size_t i = 0; i < k; ++i) out[i].kernel_ms = total_ms;
+        for (size_t i = 0; i < k; ++i)
+            if (!is_spec[i]) out[i].kernel_ms = total_ms;
+        if (!spec.empty()) {
+            const int waves = specialized_waves_per_eu();
+            std::vector<std::shared_ptr<JitKernel>> jk(spec.size());
+            std::vector<double> cms(spec.size(), 0.0);
+            std::atomic<size_t> next{0};
+            std::exception_ptr err;
+            std::mutex err_mu;
+            const size_t threads = std::min<size_t>(spec.size(), std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+            std::vector<std::thread> pool;
+            for (size_t t = 0; t < threads; ++t)
+                pool.emplace_back([&] {
+                    for (size_t j; (j = next++) < spec.size();) {
+                        try {
+                            jk[j] = jit_kernel(*v[spec[j]], waves, &cms[j]);
+                        } catch (...) {
+                            std::lock_guard<std::mutex> g(err_mu);
+                            if (!err) err = std::current_exception();
+                        }
+                    }
+                });
+            for (auto& th : pool) th.join();
+            if (err) std::rethrow_exception(err);
+            for (size_t j = 0; j < spec.size(); ++j) {
+                const size_t i = spec[j];
+                uint64_t best = ~0ull;
+                double ms = 0;
+                run_jit(dev, *v[i], *jk[j], rs[i], o.tile_words ? 2ull * o.tile_words : 0, stream, nullptr, &best, &ms);
+                std::memset(&out[i], 0, sizeof(out[i]));
+                fill_result(*v[i], rs[i], best, &out[i]);
+                out[i].kernel_ms = ms;
+                out[i].compile_ms = cms[j];
+            }
+        }
         return FASTLEC_OK;
     });
 }
@@ -398,6 +451,24 @@ int fastlec_es_submiter_aag(const fastlec_es_circuit* c, const uint32_t* class_o
         if (buf) {
             if (len < text.size() + 1) throw Error{kErrInvalid, "buffer too small"};
             std::memcpy(buf, text.c_str(), text.size() + 1);
+        }
+        return FASTLEC_OK;
+    });
+}
+
+int fastlec_es_predict(const fastlec_es_circuit* c, uint64_t begin_word, uint64_t end_word, double* interp_ms,
+                       double* specialized_ms, double* compile_ms) {
+    return guarded([&] {
+        if (!c) throw Error{kErrInvalid, "null circuit"};
+        Circuit& cc = const_cast<Circuit&>(c->c);
+        const HwRange r = range_of(cc.plan1.num_inputs, begin_word, end_word);
+        const double patterns = 32.0 * (double)(r.end - r.begin);
+        if (interp_ms)
+            *interp_ms = model_interp_ms(std::max<uint32_t>(1, cc.plan1.num_gate_instrs), cc.plan1.peak_slots, patterns);
+        if (specialized_ms || compile_ms) {
+            const uint32_t luts = cc.lut_program().lut_steps;
+            if (specialized_ms) *specialized_ms = model_specialized_ms(luts, patterns);
+            if (compile_ms) *compile_ms = model_compile_ms(luts);
         }
         return FASTLEC_OK;
     });

@@ -137,6 +137,16 @@ Schedule default_schedule(Device& dev, const std::vector<Circuit*>& cs, const fa
 bool make_schedule(Device& dev, const std::vector<Circuit*>& cs, int K, int B, int block, bool lds, Schedule& out);
 bool make_schedule_rows(Device& dev, uint32_t rows, int K, int B, int block, bool lds, Schedule& out);
 
+// Runtime model of exact simulation on MI355X (the paper's form: linear in the gate count,
+// exponential in the input count, Section 3.2, runtime prediction), per kernel, with a fixed
+// launch cost; constants fitted by least squares on measured plain checks (32 cones, n 12..32).
+//  interpreter:  t = t0 + N * max(patterns / R, L), R by value-file size (S slots)
+//  specialized:  t = t0 + LUT steps * passes / R, passes = patterns / 2048 (at least 1)
+//  compile:      t = c0 + c1 * LUT steps
+double model_interp_ms(uint32_t gates, uint32_t slots, double patterns);
+double model_specialized_ms(uint32_t lut_steps, double patterns);
+double model_compile_ms(uint32_t lut_steps);
+
 // Sub-miter of candidate pair (target, class_of[target]) by virtual sweeping, as ASCII AIGER;
 // inputs (if not null) receives the original input index of each sub-miter input.
 std::string submiter_aag(const Aig& g, const uint32_t* class_of, const uint8_t* polarity, uint64_t rows,

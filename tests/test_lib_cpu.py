@@ -158,3 +158,21 @@ def test_simulation_argument_errors_without_gpu():
         with pytest.raises(es.EsError) as ei:
             call()
         assert ei.value.code == -5
+
+
+def test_runtime_model_properties():
+    """fastlec_es_predict (host only): the paper's form, linear in gates and exponential in
+    inputs beyond the fixed costs; the compile estimate does not depend on the range."""
+    g = miters.layered_cone_miter(44, 30, 3000)
+    c = es.fastlec_es_load_aig(g.to_aig())
+    full = es.fastlec_es_predict(c)
+    half = es.fastlec_es_predict(c, 0, 1 << (30 - 7))   # half the 2^24 64-bit words
+    assert all(v > 0 for v in full.values())
+    assert full["interp_ms"] > full["specialized_ms"]
+    assert 1.9 < full["interp_ms"] / half["interp_ms"] <= 2.0
+    assert 1.9 < full["specialized_ms"] / half["specialized_ms"] <= 2.0
+    assert full["compile_ms"] == half["compile_ms"] > 100
+    small = es.fastlec_es_load_aig(miters.layered_cone_miter(44, 30, 1000).to_aig())
+    assert es.fastlec_es_predict(small)["interp_ms"] < full["interp_ms"]
+    with pytest.raises(es.EsError):
+        es.fastlec_es_predict(c, 5, 3)

@@ -1,0 +1,62 @@
+"""The runtime model against measured kernel times, and the batch's use of it.
+
+The paper predicts ES time from the gate and input counts with coefficients fitted
+on measurements (Section 3.2, runtime prediction) and uses the prediction to pick
+engines.  The library fits that form per kernel on MI355X (paper_2512_06627_amd/
+calibrate.py); here held-out cones (other seeds, sizes and input counts than the
+fitting set) must be predicted within a factor of two, and a batch must send the
+cones the model favours to the specialized kernel with answers equal to the oracle's.
+"""
+import pytest
+
+import miters
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def es():
+    import paper_2512_06627_amd as m
+    return m
+
+
+HELD_OUT = [(5, 21, 2500), (6, 23, 700), (7, 25, 4000), (8, 27, 1500), (9, 19, 6000)]
+
+
+@pytest.mark.parametrize("seed,n,gates", HELD_OUT)
+def test_predictions_within_factor_two(seed, n, gates):
+    E = es()
+    c = E.fastlec_es_load_aig(miters.layered_cone_miter(seed, n, gates).to_aig())
+    p = E.fastlec_es_predict(c)
+    for kern in ("interp", "specialized"):
+        r = E.fastlec_es_check(c, kernel=kern)
+        if kern == "specialized":
+            assert 0.5 < p["compile_ms"] / max(r["compile_ms"], 1e-3) < 2.0 or r["compile_ms"] == 0
+        ms = sorted(E.fastlec_es_check(c, kernel=kern)["kernel_ms"] for _ in range(5))[2]
+        assert 0.5 < p[kern + "_ms"] / ms < 2.0, (kern, p[kern + "_ms"], ms)
+
+
+def test_batch_routes_large_cones_to_specialized_kernel():
+    E = es()
+    gs = [miters.layered_cone_miter(60 + i, 14 + i % 3, 300) for i in range(6)]
+    gs += [miters.mult_miter(12, "booth"), miters.mult_miter(12, "booth", fault_seed=3),
+           miters.layered_cone_miter(72, 30, 6000), miters.layered_cone_miter(73, 31, 4000, fault_seed=2)]
+    cs = [E.fastlec_es_load_aig(g.to_aig()) for g in gs]
+    res = E.fastlec_es_check_batch(cs)
+    want_spec = []
+    for c in cs:
+        p = E.fastlec_es_predict(c)
+        want_spec.append(p["specialized_ms"] + 1.5 * p["compile_ms"] < p["interp_ms"])
+    assert any(want_spec) and not all(want_spec)
+    for g, c, r, ws in zip(gs, cs, res, want_spec):
+        # a routed cone's kernel is compiled already; compiling again costs nothing
+        if ws:
+            assert E.fastlec_es_compile_specialized(c, 3)["compile_ms"] == 0
+        if g.num_inputs <= 24:
+            want = oracle.check(g.to_aag(), threads=16)
+            assert (r["verdict"] == E.FASTLEC_EQUIVALENT) == (want is None)
+            if want is not None:
+                assert r["cex"] == want
+        alone = E.fastlec_es_check(c, kernel="interp")
+        assert (r["verdict"], r["cex"]) == (alone["verdict"], alone["cex"])
