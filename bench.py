@@ -291,6 +291,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (HBM counter calibration)")
+    ap.add_argument("--leg", choices=["rsim", "sweep"], default=None,
+                    help="run only this secondary leg (random simulation or a sweeping pass) and print its JSON")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only: exact simulation here is a single-GPU build "
@@ -309,6 +311,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if a.leg:
+        leg = {"rsim": rsim_leg, "sweep": sweep_leg}[a.leg]
+        print(json.dumps({"leg": a.leg, **leg(es, stream)}), flush=True)
+        return
     g = miters.workload(a.workload)
     aig = g.to_aig()
     t0 = time.perf_counter()
