@@ -122,8 +122,9 @@ int fastlec_es_check(const fastlec_es_circuit *c, const fastlec_es_options *opts
 
 /* Exact simulation of k circuits of different sizes and input counts (whole space each; the
  * option's word range is ignored).  With kernel AUTO, circuits that the runtime model
- * (fastlec_es_predict) gives to the specialized kernel are compiled in parallel host threads
- * and run as their own launches (kernel_ms and compile_ms their own).  The others are grouped
+ * (fastlec_es_predict) gives to the specialized kernel are compiled together (up to 64 kernels
+ * per hipRTC program) and run as their own launches (kernel_ms their own, compile_ms their
+ * share of their program's compile).  The others are grouped
  * by value-file size (powers of two of the row count); each group is one persistent
  * interpreter launch over all its cones, in longest-processing-time order, with a tuned
  * schedule (or the option's schedule fields) and recorded once as a hipGraph; their kernel_ms
@@ -271,6 +272,14 @@ int fastlec_es_predict(const fastlec_es_circuit *c, uint64_t begin_word, uint64_
  * the code object. */
 int fastlec_es_compile_specialized(const fastlec_es_circuit *c, int waves_per_eu, double *compile_ms,
                                    size_t *code_bytes);
+
+/* Compile the specialized kernels of k circuits together, as few hipRTC programs as possible
+ * (up to 64 kernels each, every kernel under its own entry point), without running them; no GPU
+ * needed.  Kernels already compiled or cached are reused.  hipRTC's fixed cost (about 0.1 s per
+ * program) is paid once per program instead of once per circuit.  *compile_ms (may be NULL) =
+ * total compile time paid by this call.  Later checks of these circuits use the kernels. */
+int fastlec_es_compile_specialized_many(const fastlec_es_circuit *const *cs, size_t k, int waves_per_eu,
+                                        double *compile_ms);
 
 /* Copy the specialized kernel's HIP source into buf (len bytes, NUL-terminated, truncated
  * to fit) and return the length it needs including the NUL.  buf may be NULL. */

@@ -100,6 +100,8 @@ SIGNATURES = [
     ("fastlec_es_server_destroy", None, [_P]),
     ("fastlec_es_compile_specialized", ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                                       ctypes.POINTER(ctypes.c_size_t)]),
+    ("fastlec_es_compile_specialized_many", ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_size_t, ctypes.c_int,
+                                                           ctypes.POINTER(ctypes.c_double)]),
     ("fastlec_es_specialized_source", ctypes.c_size_t, [_P, ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t]),
     ("fastlec_es_host_replay", ctypes.c_int, [_P, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
                                               ctypes.POINTER(ctypes.c_uint32)]),
@@ -245,6 +247,17 @@ def fastlec_es_compile_specialized(circuit: Circuit, waves_per_eu: int = 2):
     if rc:
         _raise(rc)
     return {"compile_ms": ms.value, "code_bytes": size.value}
+
+
+def fastlec_es_compile_specialized_many(circuits, waves_per_eu: int = 3) -> float:
+    """Compile the specialized kernels of several circuits as few hipRTC programs; returns the
+    compile time paid (ms)."""
+    arr = (ctypes.c_void_p * len(circuits))(*[c.handle.value for c in circuits])
+    ms = ctypes.c_double()
+    rc = lib().fastlec_es_compile_specialized_many(arr, len(circuits), waves_per_eu, ctypes.byref(ms))
+    if rc:
+        _raise(rc)
+    return ms.value
 
 
 def fastlec_es_specialized_source(circuit: Circuit, waves_per_eu: int = 2) -> str:

@@ -8,7 +8,6 @@
 #include <unordered_map>
 #include <fstream>
 #include <sstream>
-#include <thread>
 
 #include "runtime.hpp"
 
@@ -226,17 +225,39 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
             v.push_back(const_cast<Circuit*>(&cs[i]->c));
             rs.push_back(range_of(v.back()->plan1.num_inputs, 0, 0));
         }
-        // Cones the runtime model gives to the specialized kernel (AUTO only) are compiled in
-        // parallel host threads and run as their own launches; the rest share interpreter
-        // launches.
+        // Cones the runtime model gives to the specialized kernel (AUTO only) run as their own
+        // launches; the rest share interpreter launches.  Their kernels compile together as
+        // few hipRTC programs, so a cone is a candidate when its predicted saving beats its
+        // own share of the compile (margin 1.5 on the per-LUT part), and the candidates are
+        // taken when their summed saving also covers one program's fixed cost (same margin).
         std::vector<size_t> spec;
         std::vector<uint8_t> is_spec(k, 0);
-        if (o.kernel == FASTLEC_KERNEL_AUTO)
-            for (size_t i = 0; i < k; ++i)
-                if (use_specialized(*v[i], o, rs[i])) {
+        if (o.kernel == FASTLEC_KERNEL_AUTO) {
+            double saving = 0;
+            for (size_t i = 0; i < k; ++i) {
+                Circuit& c = *v[i];
+                const double patterns = 32.0 * (double)(rs[i].end - rs[i].begin);
+                const double ti = model_interp_ms(std::max<uint32_t>(1, c.plan1.num_gate_instrs), c.plan1.peak_slots, patterns);
+                if (ti < kCompileMargin * (model_compile_ms(0) / 64.0)) continue;  // cheap cone: no LUT program
+                const uint32_t luts = c.lut_program().lut_steps;
+                const double ts = model_specialized_ms(luts, patterns);
+                const double own = jit_ready(c, specialized_waves_per_eu()) ? 0.0
+                                   : kCompileMargin * (model_compile_ms(luts) - model_compile_ms(0));
+                if (ts + own < ti) {
                     is_spec[i] = 1;
                     spec.push_back(i);
+                    saving += ti - ts - own;
                 }
+            }
+            if (saving < kCompileMargin * model_compile_ms(0)) {
+                std::vector<size_t> kept;
+                for (size_t i : spec) {  // not worth a program: only cones already compiled stay
+                    if (jit_ready(*v[i], specialized_waves_per_eu())) kept.push_back(i);
+                    else is_spec[i] = 0;
+                }
+                spec.swap(kept);
+            }
+        }
         // Groups by value-file size: one launch sizes every wave's file for its largest cone,
         // so cones with few rows would otherwise run at the occupancy of the largest.  Rows
         // are bucketed by powers of two; each group gets its own schedule and recorded launch,
@@ -277,27 +298,10 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
         for (size_t i = 0; i < k; ++i)
             if (!is_spec[i]) out[i].kernel_ms = total_ms;
         if (!spec.empty()) {
-            const int waves = specialized_waves_per_eu();
-            std::vector<std::shared_ptr<JitKernel>> jk(spec.size());
-            std::vector<double> cms(spec.size(), 0.0);
-            std::atomic<size_t> next{0};
-            std::exception_ptr err;
-            std::mutex err_mu;
-            const size_t threads = std::min<size_t>(spec.size(), std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
-            std::vector<std::thread> pool;
-            for (size_t t = 0; t < threads; ++t)
-                pool.emplace_back([&] {
-                    for (size_t j; (j = next++) < spec.size();) {
-                        try {
-                            jk[j] = jit_kernel(*v[spec[j]], waves, &cms[j]);
-                        } catch (...) {
-                            std::lock_guard<std::mutex> g(err_mu);
-                            if (!err) err = std::current_exception();
-                        }
-                    }
-                });
-            for (auto& th : pool) th.join();
-            if (err) std::rethrow_exception(err);
+            std::vector<Circuit*> sc;
+            for (size_t i : spec) sc.push_back(v[i]);
+            std::vector<double> cms;
+            const std::vector<std::shared_ptr<JitKernel>> jk = jit_kernels(sc, specialized_waves_per_eu(), &cms);
             for (size_t j = 0; j < spec.size(); ++j) {
                 const size_t i = spec[j];
                 uint64_t best = ~0ull;
@@ -325,7 +329,7 @@ int fastlec_es_compile_specialized(const fastlec_es_circuit* c, int waves_per_eu
         double ms = 0;
         auto k = jit_kernel(const_cast<Circuit&>(c->c), waves_per_eu, &ms);
         if (compile_ms) *compile_ms = ms;
-        if (code_bytes) *code_bytes = k->code.size();
+        if (code_bytes) *code_bytes = k->code->bytes->size();
         return FASTLEC_OK;
     });
 }
@@ -470,6 +474,25 @@ int fastlec_es_predict(const fastlec_es_circuit* c, uint64_t begin_word, uint64_
             if (specialized_ms) *specialized_ms = model_specialized_ms(luts, patterns);
             if (compile_ms) *compile_ms = model_compile_ms(luts);
         }
+        return FASTLEC_OK;
+    });
+}
+
+int fastlec_es_compile_specialized_many(const fastlec_es_circuit* const* cs, size_t k, int waves_per_eu,
+                                        double* compile_ms) {
+    return guarded([&] {
+        if (k && !cs) throw Error{kErrInvalid, "null argument"};
+        if (waves_per_eu < 1 || waves_per_eu > 8) throw Error{kErrInvalid, "waves_per_eu must be 1..8"};
+        std::vector<Circuit*> v;
+        for (size_t i = 0; i < k; ++i) {
+            if (!cs[i]) throw Error{kErrInvalid, "null circuit"};
+            v.push_back(const_cast<Circuit*>(&cs[i]->c));
+        }
+        std::vector<double> ms;
+        jit_kernels(v, waves_per_eu, &ms);
+        double total = 0;
+        for (double x : ms) total += x;
+        if (compile_ms) *compile_ms = total;
         return FASTLEC_OK;
     });
 }

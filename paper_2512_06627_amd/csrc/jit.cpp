@@ -307,11 +307,34 @@ std::vector<char> compile(const std::string& src, double* ms) {
     return code;
 }
 
-// Process-wide code-object cache keyed by source hash (circuits with identical plans share it).
+// Process-wide code-object cache keyed by the hash of a kernel's own source (circuits with
+// identical plans share it): the code object's bytes and the kernel's entry point in them.
+struct CachedCode {
+    std::shared_ptr<const std::vector<char>> bytes;
+    std::string name;
+};
 std::mutex g_cache_mu;
-std::map<uint64_t, std::vector<char>>& code_cache() {
-    static std::map<uint64_t, std::vector<char>> m;
+std::map<uint64_t, CachedCode>& code_cache() {
+    static std::map<uint64_t, CachedCode> m;
     return m;
+}
+
+bool from_cache(JitKernel& k) {
+    std::lock_guard<std::mutex> cg(g_cache_mu);
+    auto it = code_cache().find(k.hash);
+    if (it == code_cache().end()) return false;
+    k.code = std::make_shared<CodeObject>();
+    k.code->bytes = it->second.bytes;
+    k.name = it->second.name;
+    return true;
+}
+
+// The kernel's source with its entry point renamed (several kernels in one program).
+std::string renamed(const std::string& src, const std::string& name) {
+    const std::string from = "\nfes_es_kernel(";
+    const size_t at = src.find(from);
+    if (at == std::string::npos) throw Error{kErrInvalid, "specialized source without its entry point"};
+    return src.substr(0, at) + "\n" + name + "(" + src.substr(at + from.size());
 }
 
 }  // namespace
@@ -342,7 +365,7 @@ std::shared_ptr<JitKernel> jit_ready(Circuit& c, int waves_per_eu) {
     if (it == c.jit.end()) return nullptr;
     std::unique_lock<std::mutex> gk(it->second->mu, std::try_to_lock);
     if (!gk.owns_lock()) return nullptr;
-    return it->second->code.empty() ? nullptr : it->second;
+    return it->second->code ? it->second : nullptr;
 }
 
 std::shared_ptr<JitKernel> jit_kernel(Circuit& c, int waves_per_eu, double* compile_ms) {
@@ -358,29 +381,121 @@ std::shared_ptr<JitKernel> jit_kernel(Circuit& c, int waves_per_eu, double* comp
         c.jit[waves_per_eu] = k;
     }
     std::lock_guard<std::mutex> g(k->mu);
-    if (!k->code.empty()) return k;
+    if (k->code) return k;
     k->source = jit_source(c.lut_program(), waves_per_eu, k->block, &k->waves_used);
     k->hash = fnv1a(k->source);
-    {
-        std::lock_guard<std::mutex> cg(g_cache_mu);
-        auto it = code_cache().find(k->hash);
-        if (it != code_cache().end()) k->code = it->second;
-    }
-    if (k->code.empty()) {
+    if (!from_cache(*k)) {
         trace("specialized: compiling %zu bytes of source", k->source.size());
+        auto obj = std::make_shared<CodeObject>();
         try {
-            k->code = compile(k->source, &k->compile_ms);
+            obj->bytes = std::make_shared<const std::vector<char>>(compile(k->source, &k->compile_ms));
         } catch (...) {
             std::lock_guard<std::mutex> cg(c.mu);
             c.jit.erase(waves_per_eu);
             throw;
         }
+        k->code = obj;
+        k->name = "fes_es_kernel";
         if (compile_ms) *compile_ms = k->compile_ms;
-        trace("specialized: compiled in %.0f ms, %zu bytes of code", k->compile_ms, k->code.size());
+        trace("specialized: compiled in %.0f ms, %zu bytes of code", k->compile_ms, obj->bytes->size());
         std::lock_guard<std::mutex> cg(g_cache_mu);
-        code_cache()[k->hash] = k->code;
+        code_cache()[k->hash] = {obj->bytes, k->name};
     }
     return k;
+}
+
+std::vector<std::shared_ptr<JitKernel>> jit_kernels(const std::vector<Circuit*>& cs, int waves_per_eu,
+                                                    std::vector<double>* compile_ms) {
+    const size_t m = cs.size();
+    std::vector<std::shared_ptr<JitKernel>> ks(m);
+    if (compile_ms) compile_ms->assign(m, 0.0);
+    // Each circuit's kernel object; their locks are taken in circuit order (uids never repeat),
+    // so two callers with overlapping circuit sets cannot deadlock.
+    std::vector<size_t> order(m);
+    for (size_t i = 0; i < m; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cs[a]->uid < cs[b]->uid; });
+    std::vector<std::unique_lock<std::mutex>> locks;
+    std::vector<size_t> pending;
+    for (size_t i : order) {
+        Circuit& c = *cs[i];
+        {
+            std::lock_guard<std::mutex> g(c.mu);
+            auto it = c.jit.find(waves_per_eu);
+            if (it == c.jit.end()) {
+                auto k = std::make_shared<JitKernel>();
+                k->waves_per_eu = waves_per_eu;
+                k->block = specialized_block();
+                it = c.jit.emplace(waves_per_eu, k).first;
+            }
+            ks[i] = it->second;
+        }
+        bool dup = false;
+        for (auto& l : locks) dup |= l.mutex() == &ks[i]->mu;
+        if (dup) continue;  // the same circuit twice
+        locks.emplace_back(ks[i]->mu);
+        JitKernel& k = *ks[i];
+        if (k.code) continue;
+        k.source = jit_source(c.lut_program(), waves_per_eu, k.block, &k.waves_used);
+        k.hash = fnv1a(k.source);
+        if (!from_cache(k)) pending.push_back(i);
+    }
+    // Programs of at most 64 kernels, each under its own entry-point name.
+    constexpr size_t kPerProgram = 64;
+    for (size_t p0 = 0; p0 < pending.size(); p0 += kPerProgram) {
+        const size_t p1 = std::min(pending.size(), p0 + kPerProgram);
+        std::string src;
+        size_t bytes = 0;
+        for (size_t t = p0; t < p1; ++t) {
+            JitKernel& k = *ks[pending[t]];
+            k.name = "fes_es_kernel_" + std::to_string(t - p0);
+            src += renamed(k.source, k.name);
+            bytes += k.source.size();
+        }
+        double ms = 0;
+        auto obj = std::make_shared<CodeObject>();
+        try {
+            trace("specialized: compiling %zu kernels in one program (%zu bytes of source)", p1 - p0, bytes);
+            obj->bytes = std::make_shared<const std::vector<char>>(compile(src, &ms));
+        } catch (...) {
+            for (size_t t = p0; t < pending.size(); ++t) {
+                Circuit& c = *cs[pending[t]];
+                std::lock_guard<std::mutex> g(c.mu);
+                c.jit.erase(waves_per_eu);
+            }
+            throw;
+        }
+        trace("specialized: compiled %zu kernels in %.0f ms", p1 - p0, ms);
+        std::lock_guard<std::mutex> cg(g_cache_mu);
+        for (size_t t = p0; t < p1; ++t) {
+            JitKernel& k = *ks[pending[t]];
+            k.code = obj;
+            k.compile_ms = ms / (double)(p1 - p0);
+            if (compile_ms) (*compile_ms)[pending[t]] = k.compile_ms;
+            code_cache()[k.hash] = {obj->bytes, k.name};
+        }
+    }
+    return ks;
+}
+
+hipModule_t CodeObject::module(int device) {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = modules.find(device);
+    if (it != modules.end()) return it->second;
+    hipModule_t mod;
+    trace("specialized: loading a code object of %zu bytes on device %d", bytes->size(), device);
+    FES_HIP(hipModuleLoadData(&mod, bytes->data()));
+    modules[device] = mod;
+    return mod;
+}
+
+CodeObject::~CodeObject() {
+    for (auto& dm : modules) {
+        int cur = 0;
+        if (hipGetDevice(&cur) == hipSuccess && hipSetDevice(dm.first) == hipSuccess) {
+            (void)hipModuleUnload(dm.second);
+            (void)hipSetDevice(cur);
+        }
+    }
 }
 
 JitLaunchPlan jit_prepare(Device& dev, JitKernel& k, const HwRange& r, uint64_t tile_hw) {
@@ -390,11 +505,8 @@ JitLaunchPlan jit_prepare(Device& dev, JitKernel& k, const HwRange& r, uint64_t 
         std::lock_guard<std::mutex> g(k.mu);
         auto it = k.per_device.find(dev.ordinal);
         if (it == k.per_device.end()) {
-            hipModule_t mod;
             hipFunction_t fn;
-            trace("specialized: loading module on device %d", dev.ordinal);
-            FES_HIP(hipModuleLoadData(&mod, k.code.data()));
-            FES_HIP(hipModuleGetFunction(&fn, mod, "fes_es_kernel"));
+            FES_HIP(hipModuleGetFunction(&fn, k.code->module(dev.ordinal), k.name.c_str()));
             int b = 0;
             FES_HIP(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, k.block, 0));
             // The persistent grid holds the targeted waves per SIMD (a workgroup of `block`
@@ -402,10 +514,10 @@ JitLaunchPlan jit_prepare(Device& dev, JitKernel& k, const HwRange& r, uint64_t 
             // register count decides whether one more wave would fit, and at four waves per
             // SIMD the 16x16 kernel runs a third slower than at three.
             const int target = std::max(1, k.waves_used * 4 * 64 / k.block);
-            k.per_device[dev.ordinal] = {mod, fn};
+            k.per_device[dev.ordinal] = fn;
             k.blocks_per_cu[dev.ordinal] = std::max(1, std::min(b, target));
         }
-        lp.fn = k.per_device[dev.ordinal].second;
+        lp.fn = k.per_device[dev.ordinal];
         blocks_per_cu = k.blocks_per_cu[dev.ordinal];
     }
     lp.grid = dev.prop.multiProcessorCount * blocks_per_cu;

@@ -57,15 +57,7 @@ Circuit::~Circuit() {
             (void)hipSetDevice(cur);
         }
     }
-    for (auto& kv : jit) {
-        for (auto& dm : kv.second->per_device) {
-            int cur = 0;
-            if (hipGetDevice(&cur) == hipSuccess && hipSetDevice(dm.first) == hipSuccess) {
-                (void)hipModuleUnload(dm.second.first);
-                (void)hipSetDevice(cur);
-            }
-        }
-    }
+    // Specialized kernels unload their modules when their code object goes (CodeObject).
 }
 
 const Plan& Circuit::plan_for(uint32_t bundle) {

@@ -42,16 +42,27 @@ void trace(const char* fmt, ...);
 
 // A straight-line kernel compiled for one circuit (hipRTC code object) and its
 // per-device module handles.
+// A compiled code object (one or more specialized kernels) and its module on each device it was
+// loaded on; the modules are unloaded when the last kernel that uses the object goes away.
+struct CodeObject {
+    std::shared_ptr<const std::vector<char>> bytes;
+    std::mutex mu;
+    std::map<int, hipModule_t> modules;
+    hipModule_t module(int device);  // loads on first use; the device must be current
+    ~CodeObject();
+};
+
 struct JitKernel {
-    std::string source;
-    std::vector<char> code;  // code object
+    std::string source;                // the kernel's own source (entry point fes_es_kernel)
+    std::string name = "fes_es_kernel";  // entry point in the code object
+    std::shared_ptr<CodeObject> code;  // set once compiled
     uint64_t hash = 0;
     int waves_per_eu = 2;  // requested occupancy (the cache key)
     int waves_used = 2;    // occupancy the source was built for (the launch grid follows it)
     int block = 256;
     double compile_ms = 0;
     std::mutex mu;
-    std::map<int, std::pair<hipModule_t, hipFunction_t>> per_device;
+    std::map<int, hipFunction_t> per_device;
     std::map<int, int> blocks_per_cu;
 };
 
@@ -171,6 +182,12 @@ int specialized_waves_per_eu();
 int specialized_block();
 int specialized_scalar_policy();  // FASTLEC_ES_JIT_SCALAR: 0 all, 1 pure uniform only, 2 none
 std::shared_ptr<JitKernel> jit_kernel(Circuit& c, int waves_per_eu, double* compile_ms);
+// The specialized kernels of several circuits, compiled as few hipRTC programs (each kernel
+// under its own name): hipRTC's fixed cost, about 0.1 s per program, is paid once per program
+// instead of once per circuit.  Kernels already compiled or cached are reused.  compile_ms (if
+// not null) receives each circuit's share of the compile time (0 for reused kernels).
+std::vector<std::shared_ptr<JitKernel>> jit_kernels(const std::vector<Circuit*>& cs, int waves_per_eu,
+                                                    std::vector<double>* compile_ms);
 // The circuit's specialized kernel if it is already compiled, else null.  Never compiles and
 // never waits: a kernel whose compile is in progress counts as not ready.
 std::shared_ptr<JitKernel> jit_ready(Circuit& c, int waves_per_eu);

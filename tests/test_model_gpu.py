@@ -60,3 +60,18 @@ def test_batch_routes_large_cones_to_specialized_kernel():
                 assert r["cex"] == want
         alone = E.fastlec_es_check(c, kernel="interp")
         assert (r["verdict"], r["cex"]) == (alone["verdict"], alone["cex"])
+
+
+def test_kernels_compiled_together_give_oracle_answers():
+    """Kernels from one multi-kernel hipRTC program, launched by their own entry points."""
+    E = es()
+    gs = [miters.layered_cone_miter(90 + i, 16 + i % 4, 800, fault_seed=(i if i % 2 else None)) for i in range(8)]
+    cs = [E.fastlec_es_load_aig(g.to_aig()) for g in gs]
+    assert E.fastlec_es_compile_specialized_many(cs, 3) > 0
+    for g, c in zip(gs, cs):
+        r = E.fastlec_es_check(c, kernel="specialized")
+        assert r["compile_ms"] == 0
+        want = oracle.check(g.to_aag(), threads=16)
+        assert (r["verdict"] == E.FASTLEC_EQUIVALENT) == (want is None)
+        if want is not None:
+            assert r["cex"] == want
