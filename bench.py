@@ -87,8 +87,11 @@ def cpu_baseline(aag: bytes, num_ands: int, target_s: float = 12.0):
 def batch_leg(es, stream, seed: int = 4, count: int = 256, faulty: int = 26, n_range=(18, 30),
               size_range=(200, 5000)):
     """`count` XOR-dense layered cones (n ~ U{n_range}, ~U[size_range] AND gates, `faulty` of them
-    with an injected fault): one persistent batched launch (autotuned, hipGraph) vs one plain
-    check per cone, both on the interpreter kernel."""
+    with an injected fault), checked four ways with identical answers: one plain check per cone on
+    the interpreter; one batched call on the interpreter (persistent grouped launches, autotuned,
+    hipGraph); one batched call with the runtime model's routing (large cones on their compiled
+    specialized kernels, compiled together on the first call); one plain check per cone with the
+    model's kernel choice once those kernels exist."""
     import miters
     rng = miters.SplitMix64(seed)
     bad = set()
@@ -108,24 +111,31 @@ def batch_leg(es, stream, seed: int = 4, count: int = 256, faulty: int = 26, n_r
     def answers(rs):
         return [r["cex"] if r["verdict"] == es.FASTLEC_NONEQUIVALENT else None for r in rs]
 
+    def timed(f, reps):
+        ts, out = [], None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            out = f()
+            ts.append(time.perf_counter() - t0)
+        return sorted(ts)[len(ts) // 2], out
+
     plain = answers([es.fastlec_es_check(c, stream=stream, kernel="interp") for c in cones])  # warm: uploads
+    t_plain, plain2 = timed(lambda: answers([es.fastlec_es_check(c, stream=stream, kernel="interp") for c in cones]), 1)
+    interp_first = answers(es.fastlec_es_check_batch(cones, stream=stream, kernel="interp"))  # autotune + capture
+    t_batch_interp, got_interp = timed(lambda: answers(es.fastlec_es_check_batch(cones, stream=stream, kernel="interp")), 3)
     t0 = time.perf_counter()
-    plain2 = answers([es.fastlec_es_check(c, stream=stream, kernel="interp") for c in cones])
-    t_plain = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    first = answers(es.fastlec_es_check_batch(cones, stream=stream))  # autotune + graph capture
+    first = answers(es.fastlec_es_check_batch(cones, stream=stream))  # compiles + autotune + capture
     t_first = time.perf_counter() - t0
-    reps = []
-    for _ in range(3):
-        t0 = time.perf_counter()
-        got = answers(es.fastlec_es_check_batch(cones, stream=stream))
-        reps.append(time.perf_counter() - t0)
-    t_batch = sorted(reps)[1]
-    return {"cones": count, "n_range": list(n_range), "gates_range": list(size_range), "faulty_injected": faulty, "found_nonequivalent": sum(a is not None for a in got),
-            "node_patterns_upper_bound": work, "plain_cones_per_s": count / t_plain,
+    t_batch, got = timed(lambda: answers(es.fastlec_es_check_batch(cones, stream=stream)), 3)
+    t_plain_auto, plain_auto = timed(lambda: answers([es.fastlec_es_check(c, stream=stream) for c in cones]), 1)
+    return {"cones": count, "n_range": list(n_range), "gates_range": list(size_range), "faulty_injected": faulty,
+            "found_nonequivalent": sum(a is not None for a in got), "node_patterns_upper_bound": work,
+            "plain_cones_per_s": count / t_plain, "batched_interp_cones_per_s": count / t_batch_interp,
+            "batched_interp_vs_plain_speedup": t_plain / t_batch_interp,
             "batched_cones_per_s": count / t_batch, "batched_vs_plain_speedup": t_plain / t_batch,
-            "identical_verdicts": plain == plain2 == first == got, "first_batch_call_s": t_first,
-            "generate_s": gen_s}
+            "plain_auto_cones_per_s": count / t_plain_auto, "batched_vs_plain_auto_speedup": t_plain_auto / t_batch,
+            "identical_verdicts": plain == plain2 == interp_first == got_interp == first == got == plain_auto,
+            "first_batch_call_s": t_first, "generate_s": gen_s}
 
 
 def rsim_leg(es, stream, workload: str = "mult16_array_booth", words: int = 1 << 18, reps: int = 5):
