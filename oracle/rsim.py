@@ -48,6 +48,8 @@ def read_aag(aag: bytes):
         lhs, r0, r1 = map(int, lines[1 + I + O + k].split())
         if lhs != 2 * (I + 1 + k):
             raise ValueError("AND gates must define variables n+1..M in order")
+        if max(r0, r1) >= lhs:
+            raise ValueError("an AND gate reads a variable not defined before it")
         ands.append((lhs >> 1, r0, r1))
     if M != I + A:
         raise ValueError("header M must equal I + A")

@@ -175,3 +175,31 @@ def test_invalid_arguments():
         E.fastlec_es_simulate(c, sig, 0, sig)      # no words
     with pytest.raises(E.EsError):
         E.fastlec_es_signature_hash(sig, 0, 8, sig, sig)
+
+
+def _hand_files():
+    import os
+    d = os.path.join(os.path.dirname(__file__), "golden", "hand")
+    out = []
+    for f in sorted(os.listdir(d)):
+        b = open(os.path.join(d, f), "rb").read()
+        try:
+            rsim.read_aag(b)
+        except ValueError:
+            continue  # not a canonical latch-free file (out-of-order lines, latches, cycles, ...)
+        out.append((f, b))
+    return out
+
+
+@pytest.mark.parametrize("name,text", _hand_files(), ids=[f for f, _ in _hand_files()])
+@pytest.mark.parametrize("W", [1, 70])
+def test_hand_worked_files(name, text, W):
+    """Constant outputs, zero inputs, multi-output and inverted outputs (hand-worked files)."""
+    n = rsim.read_aag(text)[0]
+    words = words_of(n, W, seed=len(name) + W)
+    sig, _ = gpu_sim(text, words)
+    want = rsim.simulate(text, words)
+    assert np.array_equal(sig.cpu().numpy().view(np.uint32), want)
+    h, ones = gpu_hash(sig)
+    wh, wones = rsim.signature_hash(want)
+    assert np.array_equal(h, wh) and np.array_equal(ones, wones)

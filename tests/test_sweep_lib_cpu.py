@@ -89,3 +89,23 @@ def test_errors():
     bad[8] = 6
     with pytest.raises(es.EsError):
         es.fastlec_es_submiter_aag(c, bad, pol, 8)
+
+
+def test_representatives_that_are_inputs_or_constants():
+    """pi_and_const.aag: var4 = a & ~(~a & ~b) equals input a, var5 = a & ~a is constant false,
+    var6 = var4 & ~var5 equals a.  Sub-miters then hold input and constant literals; the library
+    writes the oracle's text and every sub-miter is equivalent (the classes are exact)."""
+    import oracle
+    text = open(os.path.join(GOLD, "pi_and_const.aag"), "rb").read()
+    cls, pol = classes_and_polarity(text, exhaustive_words(2))
+    assert cls.tolist() == [0, 1, 2, 3, 1, 0, 1]
+    c = es.fastlec_es_load_aig(text)
+    ts = sweep.targets(cls.tolist(), 2)
+    assert ts == [4, 5, 6]
+    for t in ts:
+        want = sweep.submiter_aag(text, cls.tolist(), pol.tolist(), t)
+        got = es.fastlec_es_submiter_aag(c, cls, pol, t)
+        assert got == want
+        assert oracle.check(got[0]) is None
+    # the constant target's sub-miter reads only constants and input a
+    assert sweep.submiter_aag(text, cls.tolist(), pol.tolist(), 5)[1] == [0]
