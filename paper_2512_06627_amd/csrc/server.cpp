@@ -111,36 +111,59 @@ struct fastlec_es_server {
 };
 
 void fastlec_es_server::compile_loop() {
+    // Up to this many queued jobs compile as one hipRTC program: its fixed cost (about 0.1 s)
+    // is then paid once for the group.
+    constexpr size_t kGroup = 8;
     for (;;) {
-        Job* j = nullptr;
+        std::vector<Job*> group;
         {
             std::unique_lock<std::mutex> g(mu);
             cv_compile.wait(g, [&] { return stop || !compile_queue.empty(); });
             if (stop) return;
             // Largest remaining work first: it gains the most from the specialized kernel.
-            auto pick = compile_queue.begin();
-            double most = -1;
-            for (auto it = compile_queue.begin(); it != compile_queue.end(); ++it) {
-                const double w = (double)(*it)->c->plan1.num_gate_instrs * (double)((*it)->range.end - (*it)->cursor);
-                if (!(*it)->done && w > most) {
-                    most = w;
-                    pick = it;
+            while (group.size() < kGroup && !compile_queue.empty()) {
+                auto pick = compile_queue.end();
+                double most = -1;
+                for (auto it = compile_queue.begin(); it != compile_queue.end(); ++it) {
+                    const double w = (double)(*it)->c->plan1.num_gate_instrs * (double)((*it)->range.end - (*it)->cursor);
+                    if (!(*it)->done && w > most) {
+                        most = w;
+                        pick = it;
+                    }
+                }
+                if (pick == compile_queue.end()) {  // only finished jobs are left
+                    compile_queue.clear();
+                    break;
+                }
+                Job* j = *pick;
+                compile_queue.erase(pick);
+                j->compiling = true;
+                group.push_back(j);
+            }
+            if (group.empty()) continue;
+        }
+        std::vector<Circuit*> cs;
+        for (Job* j : group) cs.push_back(j->c);
+        std::vector<std::shared_ptr<JitKernel>> ks;
+        try {
+            ks = jit_kernels(cs, specialized_waves_per_eu(), nullptr);
+        } catch (...) {
+            // one kernel that does not compile must not keep the others on the interpreter
+            ks.assign(group.size(), nullptr);
+            for (size_t t = 0; t < group.size(); ++t) {
+                try {
+                    ks[t] = jit_kernel(*cs[t], specialized_waves_per_eu(), nullptr);
+                } catch (...) {
+                    ks[t] = nullptr;  // the job stays on the interpreter
                 }
             }
-            j = *pick;
-            compile_queue.erase(pick);
-            if (j->done) continue;
-            j->compiling = true;
-        }
-        std::shared_ptr<JitKernel> k;
-        try {
-            k = jit_kernel(*j->c, specialized_waves_per_eu(), nullptr);
-        } catch (...) {
-            k = nullptr;  // the job stays on the interpreter
         }
         std::lock_guard<std::mutex> g(mu);
-        j->compiling = false;
-        if (k && !j->done) j->jit = k;
+        for (size_t t = 0; t < group.size(); ++t) {
+            Job* j = group[t];
+            j->compiling = false;
+            if (ks[t] && ks[t]->code && !j->done) j->jit = ks[t];
+        }
         cv_done.notify_all();
     }
 }
