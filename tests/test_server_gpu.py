@@ -151,3 +151,29 @@ def test_server_specialized_tier_switch_mid_job(monkeypatch):
         assert st["specialized_slices"] > 0, st
     finally:
         srv.close()
+
+
+def test_server_compiles_queued_jobs_in_groups(monkeypatch):
+    """More jobs than one compile group (eight), one circuit submitted twice in the same round:
+    the compile thread builds multi-kernel programs (the repeated circuit compiles once); in a
+    second round the compiled kernels run from the first step.  Every answer equals the circuit
+    checked alone (and the oracle's where it is cheap)."""
+    monkeypatch.setenv("FASTLEC_ES_SERVER_JIT", "2")
+    monkeypatch.setenv("FASTLEC_ES_SERVER_STEP_MS", "1")
+    gs = _jobs(47, 11, 20, 24, 800, 2000, faulty_every=3)
+    circs = [es.fastlec_es_load_aig(g.to_aig()) for g in gs]
+    alone = [_answer(es.fastlec_es_check(c, kernel="interp")) for c in circs]
+    for g, a in zip(gs, alone):
+        if g.num_inputs <= 20:
+            assert a == oracle.check(g.to_aag(), threads=16)
+    srv = es.Server(8 << 30)
+    try:
+        subs = circs + [circs[0]]
+        for rep in range(2):
+            print("submission round", rep, flush=True)
+            tickets = [srv.submit(c) for c in subs]
+            got = [_answer(srv.poll(t, wait=True)) for t in tickets]
+            assert got == alone + [alone[0]], rep
+        assert srv.stats()["specialized_slices"] > 0
+    finally:
+        srv.close()
