@@ -1,6 +1,7 @@
 // Host-only driver for sanitizer builds of the planner path: AIGER reader, slot planner,
-// LUT mapper and the block emitter.  For each AIGER file on the command line it prints one
-// line: the file's index, then the LUT program's miter word at each requested half-word.
+// LUT mapper, block emitter, simulation plan and sub-miter extraction.  For each AIGER file on
+// the command line it prints a line with the file's index and the LUT program's miter word at
+// each requested half-word, then a line "<index> sweep <targets> <FNV-1a of the sub-miters>".
 // Any memory or undefined-behaviour error aborts the run (AddressSanitizer / UBSan).
 //
 //   host_driver HW1,HW2,... file1.aig file2.aig ...
@@ -63,6 +64,58 @@ int main(int argc, char** argv) {
         std::printf("%d", f - 2);
         for (uint32_t w : words) std::printf(" %u", w);
         std::printf("\n");
+
+        // Simulation plan (every gate: outputs plus gates that feed nothing), validated.
+        Aig all = g;
+        std::vector<uint8_t> read(all.max_var() + 1, 0);
+        for (uint32_t k = 0; k < all.num_ands(); ++k) read[all.and_r0[k] >> 1] = read[all.and_r1[k] >> 1] = 1;
+        for (uint32_t o : all.outputs) read[o >> 1] = 1;
+        for (uint32_t k = 0; k < all.num_ands(); ++k)
+            if (!read[all.num_inputs + 1 + k]) all.outputs.push_back(2 * (all.num_inputs + 1 + k));
+        const Plan ps = make_plan(all, Order::Auto, 8);
+        const std::string perr = validate_plan(all, ps);
+        if (!perr.empty() || ps.num_ands_tfi != g.num_ands()) {
+            std::printf("%d simulation plan: %s\n", f - 2, perr.c_str());
+            return 1;
+        }
+        // Sub-miters: classes by equal normalised signatures over four words per input
+        // (word k of input i = (i + 1) * 0x9E3779B1 + k * 0x85EBCA77 mod 2^32), then every target.
+        const uint32_t V = g.max_var(), W = 4;
+        std::vector<uint32_t> sig((size_t)(V + 1) * W, 0);
+        for (uint32_t i = 0; i < g.num_inputs; ++i)
+            for (uint32_t k = 0; k < W; ++k) sig[(size_t)(i + 1) * W + k] = (i + 1) * 0x9E3779B1u + k * 0x85EBCA77u;
+        for (uint32_t k = 0; k < g.num_ands(); ++k) {
+            const uint32_t v = g.num_inputs + 1 + k, a = g.and_r0[k], b = g.and_r1[k];
+            for (uint32_t w = 0; w < W; ++w)
+                sig[(size_t)v * W + w] = (sig[(size_t)(a >> 1) * W + w] ^ (0u - (a & 1u))) &
+                                         (sig[(size_t)(b >> 1) * W + w] ^ (0u - (b & 1u)));
+        }
+        std::vector<uint32_t> cls(V + 1);
+        std::vector<uint8_t> pol(V + 1);
+        std::vector<std::pair<std::vector<uint32_t>, uint32_t>> seen;
+        for (uint32_t v = 0; v <= V; ++v) {
+            pol[v] = sig[(size_t)v * W] & 1u;
+            std::vector<uint32_t> norm(W);
+            for (uint32_t w = 0; w < W; ++w) norm[w] = sig[(size_t)v * W + w] ^ (0u - pol[v]);
+            cls[v] = v;
+            for (auto& e : seen)
+                if (e.first == norm) {
+                    cls[v] = e.second;
+                    break;
+                }
+            if (cls[v] == v) seen.push_back({norm, v});
+        }
+        uint64_t h = 0xcbf29ce484222325ull, targets = 0;
+        for (uint32_t v = g.num_inputs + 1; v <= V; ++v) {
+            if (cls[v] == v) continue;
+            std::vector<uint32_t> ins;
+            const std::string text = submiter_aag(g, cls.data(), pol.data(), V + 1, v, &ins);
+            const Aig back = parse_aiger((const uint8_t*)text.data(), text.size());  // must read back
+            if (back.num_inputs != ins.size()) return 1;
+            for (unsigned char ch : text) h = (h ^ ch) * 0x100000001b3ull;
+            ++targets;
+        }
+        std::printf("%d sweep %llu %llu\n", f - 2, (unsigned long long)targets, (unsigned long long)h);
     }
     return 0;
 }

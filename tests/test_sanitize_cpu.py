@@ -1,9 +1,10 @@
 """The host-side planner path built with AddressSanitizer and UndefinedBehaviorSanitizer.
 
 tests/sanitize/host_driver.cpp runs the AIGER reader, the slot planner (bundles 1, 4, 8, 16, each
-validated by symbolic replay), the LUT mapper (scalar-unit and all-VALU policies) and the block
-emitter (all option combinations) on every file, and prints the LUT program's miter words at
-chosen half-words; those must equal the oracle's.  Host code only: nothing here runs on a GPU.
+validated by symbolic replay), the LUT mapper (scalar-unit and all-VALU policies), the block
+emitter (all option combinations), the simulation plan and the sub-miter extraction of every
+candidate pair on every file, and prints the LUT program's miter words at chosen half-words and
+a hash of the sub-miters; those must equal the oracles'.  Host code only: nothing here runs on a GPU.
 """
 import json
 import os
@@ -27,7 +28,7 @@ def driver(tmp_path_factory):
         pytest.skip("clang++ not found")
     out = str(tmp_path_factory.mktemp("san") / "host_driver")
     srcs = [os.path.join(ROOT, "tests", "sanitize", "host_driver.cpp")] + [
-        os.path.join(CSRC, f) for f in ("aig.cpp", "plan.cpp", "lut.cpp", "emit_block.cpp")]
+        os.path.join(CSRC, f) for f in ("aig.cpp", "plan.cpp", "lut.cpp", "emit_block.cpp", "sweep.cpp")]
     cmd = [CLANG, "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
            "-fno-omit-frame-pointer", "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROOT, "include"),
            "-I/opt/rocm/include", "-I" + CSRC] + srcs + ["-o", out]
@@ -65,8 +66,27 @@ def test_planner_path_under_sanitizers(driver, tmp_path, golden_dir):
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1", UBSAN_OPTIONS="print_stacktrace=1")
     r = subprocess.run([driver, ",".join(map(str, hws))] + files, capture_output=True, text=True, env=env, timeout=600)
     assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-4000:])
-    lines = r.stdout.strip().splitlines()
+    out = r.stdout.strip().splitlines()
+    sweeps = [l for l in out if " sweep " in l]
+    lines = [l for l in out if " sweep " not in l]
     assert len(lines) == len(files)
+    # sub-miters of every target, from the same classes, equal the virtual-sweeping oracle's
+    from oracle import rsim, sweep
+    by_index = {int(l.split()[0]): l.split()[2:] for l in sweeps}
+    for k, (name, g) in enumerate(circs):
+        aag = g.to_aag()
+        n = g.num_inputs
+        words = np.array([[((i + 1) * 0x9E3779B1 + w * 0x85EBCA77) % (1 << 32) for w in range(4)] for i in range(n)],
+                         dtype=np.uint32).reshape(n, 4)
+        sig = rsim.simulate(aag, words)
+        cls = rsim.classes(rsim.signature_hash(sig)[0]).tolist()
+        pol = (sig[:, 0] & 1).astype(int).tolist()
+        h, count = 0xcbf29ce484222325, 0
+        for t in sweep.targets(cls, n):
+            for ch in sweep.submiter_aag(aag, cls, pol, t)[0]:
+                h = ((h ^ ch) * 0x100000001B3) % (1 << 64)
+            count += 1
+        assert by_index[k] == [str(count), str(h)], name
     for line, (name, g) in zip(lines, circs):
         fields = line.split()
         o = oracle.Circuit(g.to_aag())
