@@ -197,8 +197,9 @@ void fastlec_es_server_destroy(fastlec_es_server *s);
  *             the file's own numbering when its inputs are variables 1..n and its AND gates
  *             n+1..M in order).  Every AND gate is simulated, also gates outside the outputs'
  *             cone.  max_var = num_pis + num_ands (fastlec_es_info).
- *   opts      device, stream, words_per_thread, wg_size and kernel (FASTLEC_KERNEL_INTERP_HBM
- *             forces value files in device memory) are honoured; may be NULL.
+ *   opts      device, stream, words_per_thread (default 1; 4 uses 8-gate bundles, else 16),
+ *             wg_size and kernel (FASTLEC_KERNEL_INTERP_HBM forces value files in device memory)
+ *             are honoured; may be NULL.
  *   kernel_ms if not NULL, the kernel's time (HIP events on the launch stream).
  * Blocks until sig is written.  FASTLEC_ERR_INVALID for null pointers or num_words = 0.
  *

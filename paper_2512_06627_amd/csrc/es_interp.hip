@@ -226,9 +226,9 @@ hipError_t launch_kb(const InterpLaunch& L, bool lds, int grid, int block, hipSt
     return lds ? launch_one<K, B, true>(L, grid, block, s) : launch_one<K, B, false>(L, grid, block, s);
 }
 
-template <int K>
-hipError_t launch_sim_k(const InterpLaunch& L, bool lds, int grid, int block, hipStream_t s) {
-    return lds ? launch_one<K, 8, true, true>(L, grid, block, s) : launch_one<K, 8, false, true>(L, grid, block, s);
+template <int K, int B>
+hipError_t launch_sim_kb(const InterpLaunch& L, bool lds, int grid, int block, hipStream_t s) {
+    return lds ? launch_one<K, B, true, true>(L, grid, block, s) : launch_one<K, B, false, true>(L, grid, block, s);
 }
 
 template <int K>
@@ -248,14 +248,24 @@ size_t interp_lds_bytes(uint32_t rows, int K, int waves_per_block) {
     return (size_t)waves_per_block * rows * 64u * (size_t)K * sizeof(uint32_t);
 }
 
-hipError_t launch_interp_sim(const InterpLaunch& L, int K, bool lds, int grid, int block, hipStream_t stream) {
+hipError_t launch_interp_sim(const InterpLaunch& L, int K, int B, bool lds, int grid, int block, hipStream_t stream) {
     if (L.num_cones != 1 || !L.sim_sig || grid <= 0 || block <= 0 || block % 64) return hipErrorInvalidValue;
-    switch (K) {
-        case 1: return launch_sim_k<1>(L, lds, grid, block, stream);
-        case 2: return launch_sim_k<2>(L, lds, grid, block, stream);
-        case 4: return launch_sim_k<4>(L, lds, grid, block, stream);
-        default: return hipErrorInvalidValue;
+    if (B == 8) {
+        switch (K) {
+            case 1: return launch_sim_kb<1, 8>(L, lds, grid, block, stream);
+            case 2: return launch_sim_kb<2, 8>(L, lds, grid, block, stream);
+            case 4: return launch_sim_kb<4, 8>(L, lds, grid, block, stream);
+            default: return hipErrorInvalidValue;
+        }
     }
+    if (B == 16) {
+        switch (K) {
+            case 1: return launch_sim_kb<1, 16>(L, lds, grid, block, stream);
+            case 2: return launch_sim_kb<2, 16>(L, lds, grid, block, stream);
+            default: return hipErrorInvalidValue;  // K = 4 with 16-gate bundles spills registers
+        }
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_interp(const InterpLaunch& L, int K, int B, bool lds, int grid, int block, hipStream_t stream) {

@@ -63,9 +63,10 @@ struct InterpLaunch {
 hipError_t launch_interp(const InterpLaunch& L, int K, int B, bool lds, int grid, int block,
                          hipStream_t stream);
 
-// Simulation mode of the interpreter: one cone, bundles of 8, instruction flags = the
-// variable a gate defines (0 = store nothing).  Columns [0, sim_words) are simulated once each.
-hipError_t launch_interp_sim(const InterpLaunch& L, int K, bool lds, int grid, int block, hipStream_t stream);
+// Simulation mode of the interpreter: one cone, bundles of B (8, or 16 with K <= 2), instruction
+// flags = the variable a gate defines (0 = store nothing).  Columns [0, sim_words) are simulated
+// once each.
+hipError_t launch_interp_sim(const InterpLaunch& L, int K, int B, bool lds, int grid, int block, hipStream_t stream);
 
 // Per row of a signature matrix (rows x words, row-major): the number of ones and the
 // complement-normalised hash sum_k word'_k * (fmix32(k) | 1) mod 2^64, where word' is the

@@ -44,7 +44,7 @@ Circuit::~Circuit() {
     for (auto& kv : dev_sim_prog) {
         if (!kv.second) continue;
         int cur = 0;
-        if (hipGetDevice(&cur) == hipSuccess && hipSetDevice(kv.first) == hipSuccess) {
+        if (hipGetDevice(&cur) == hipSuccess && hipSetDevice(kv.first.first) == hipSuccess) {
             (void)hipFree(kv.second);
             (void)hipSetDevice(cur);
         }
@@ -90,8 +90,9 @@ const Instr* Circuit::device_prog(int dev, uint32_t bundle, hipStream_t s) {
     return d;
 }
 
-const Plan& Circuit::sim_plan() {
+const Plan& Circuit::sim_plan(uint32_t bundle) {
     std::lock_guard<std::mutex> g(mu);
+    std::unique_ptr<Plan>& sim = this->sim[bundle];  // bundle 8 or 16
     if (!sim) {
         Aig all = aig;
         std::vector<uint8_t> read(all.max_var() + 1, 0);
@@ -99,7 +100,7 @@ const Plan& Circuit::sim_plan() {
         for (uint32_t o : all.outputs) read[o >> 1] = 1;
         for (uint32_t k = 0; k < all.num_ands(); ++k)
             if (!read[all.num_inputs + 1 + k]) all.outputs.push_back(2 * (all.num_inputs + 1 + k));
-        sim = std::make_unique<Plan>(make_plan(all, Order::Auto, 8));
+        sim = std::make_unique<Plan>(make_plan(all, Order::Auto, bundle));
         if (sim->num_ands_tfi != aig.num_ands()) throw Error{kErrInvalid, "simulation plan misses gates"};
         const std::string err = validate_plan(all, *sim);
         if (!err.empty()) throw Error{kErrInvalid, "simulation plan: " + err};
@@ -107,10 +108,10 @@ const Plan& Circuit::sim_plan() {
     return *sim;
 }
 
-const Instr* Circuit::device_sim_prog(int dev, hipStream_t s) {
-    const Plan& p = sim_plan();
+const Instr* Circuit::device_sim_prog(int dev, uint32_t bundle, hipStream_t s) {
+    const Plan& p = sim_plan(bundle);
     std::lock_guard<std::mutex> g(mu);
-    auto it = dev_sim_prog.find(dev);
+    auto it = dev_sim_prog.find({dev, bundle});
     if (it != dev_sim_prog.end()) return it->second;
     std::vector<Instr> prog = p.prog;
     for (size_t t = 0; t < prog.size(); ++t)
@@ -121,7 +122,7 @@ const Instr* Circuit::device_sim_prog(int dev, hipStream_t s) {
         FES_HIP(hipMemcpyAsync(d, prog.data(), prog.size() * sizeof(Instr), hipMemcpyHostToDevice, s));
         FES_HIP(hipStreamSynchronize(s));
     }
-    dev_sim_prog[dev] = d;
+    dev_sim_prog[{dev, bundle}] = d;
     return d;
 }
 
@@ -393,21 +394,27 @@ double model_compile_ms(uint32_t lut_steps) { return model::kCompileC0Ms + model
 
 void run_sim(Device& dev, Circuit& c, const uint32_t* pi, uint64_t words, uint32_t* sig,
              const fastlec_es_options* o, hipStream_t stream, double* kernel_ms) {
-    const Plan& p = c.sim_plan();
+    // Bundles of 16 gates give each wave twice the independent LDS reads per wait (not with 4
+    // words per lane, which spills registers), and one word per lane leaves room for more
+    // waves: 16x16 miter, 2^18 words: 2.96 ms with 8-gate bundles and two words per lane,
+    // 2.37 ms with 16 and one.
+    int K = (o && o->words_per_thread) ? (int)o->words_per_thread : 1;
+    const char* eb = std::getenv("FASTLEC_ES_SIM_BUNDLE");
+    const uint32_t B = K == 4 || (eb && std::atoi(eb) == 8) ? 8u : 16u;
+    const Plan& p = c.sim_plan(B);
     // Schedule as a plain check would pick it (workgroup, then words per lane, shrink until a
     // workgroup's value files fit in LDS; else value files in device memory), for this plan's rows.
-    int K = (o && o->words_per_thread) ? (int)o->words_per_thread : 2;
     int block = (o && o->wg_size) ? (int)o->wg_size : 256;
     bool lds = !(o && o->kernel == FASTLEC_KERNEL_INTERP_HBM);
     if (K != 1 && K != 2 && K != 4) throw Error{kErrInvalid, "words_per_thread must be 1, 2 or 4"};
     if (block < 64 || block > 1024 || block % 64) throw Error{kErrInvalid, "wg_size must be a multiple of 64 in [64, 1024]"};
     Schedule sch;
-    while (lds && !make_schedule_rows(dev, p.rows, K, 8, block, true, sch)) {
+    while (lds && !make_schedule_rows(dev, p.rows, K, (int)B, block, true, sch)) {
         if (!(o && o->wg_size) && block > 64) block /= 2;
         else if (!(o && o->words_per_thread) && K > 1) K /= 2;
         else lds = false;
     }
-    if (!lds) make_schedule_rows(dev, p.rows, K, 8, block, false, sch);
+    if (!lds) make_schedule_rows(dev, p.rows, K, (int)B, block, false, sch);
 
     const size_t waves = (size_t)sch.grid * (sch.block / 64);
     const size_t file_bytes = sch.lds ? 0 : waves * p.rows * 64ull * sch.K * 4ull;
@@ -424,7 +431,7 @@ void run_sim(Device& dev, Circuit& c, const uint32_t* pi, uint64_t words, uint32
 
     ConeDesc& d = *(ConeDesc*)(host + lay.desc_off);
     const uint32_t pass_hw = 64u * (uint32_t)sch.K;
-    d.prog = c.device_sim_prog(dev.ordinal, stream);
+    d.prog = c.device_sim_prog(dev.ordinal, B, stream);
     d.n_instr = (uint32_t)p.prog.size();
     d.n_inputs = p.num_inputs;
     d.rows = p.rows;
@@ -461,7 +468,7 @@ void run_sim(Device& dev, Circuit& c, const uint32_t* pi, uint64_t words, uint32
           (unsigned long long)L.total_items, sch.K, sch.lds ? "lds" : "hbm", sch.grid, sch.block, p.rows);
     FES_HIP(hipMemcpyAsync(devp, host, lay.files_off, hipMemcpyHostToDevice, stream));
     FES_HIP(hipEventRecord(e0.e, stream));
-    FES_HIP(launch_interp_sim(L, sch.K, sch.lds, sch.grid, sch.block, stream));
+    FES_HIP(launch_interp_sim(L, sch.K, (int)B, sch.lds, sch.grid, sch.block, stream));
     FES_HIP(hipEventRecord(e1.e, stream));
     FES_HIP(hipStreamSynchronize(stream));
     float ms = 0;

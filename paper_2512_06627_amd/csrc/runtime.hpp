@@ -76,16 +76,16 @@ struct Circuit {
     std::map<std::pair<int, uint32_t>, Instr*> dev_prog;                  // (device, bundle) -> stream
     std::map<int, std::shared_ptr<JitKernel>> jit;                       // waves_per_eu -> kernel
     std::unique_ptr<LutProgram> lut;                                      // specialized-kernel program
-    std::unique_ptr<Plan> sim;                                            // random-simulation plan
-    std::map<int, Instr*> dev_sim_prog;                                   // device -> its stream
+    std::map<uint32_t, std::unique_ptr<Plan>> sim;                        // bundle -> simulation plan
+    std::map<std::pair<int, uint32_t>, Instr*> dev_sim_prog;              // (device, bundle) -> stream
     ~Circuit();
     const LutProgram& lut_program();
     const Plan& plan_for(uint32_t bundle);
     const Instr* device_prog(int device, uint32_t bundle, hipStream_t s);
     // Simulation covers every AND gate: the plan is made for the outputs plus every gate
-    // that feeds nothing, in bundles of 8; each gate instruction's flags hold its variable.
-    const Plan& sim_plan();
-    const Instr* device_sim_prog(int device, hipStream_t s);
+    // that feeds nothing, in bundles of `bundle`; each gate instruction's flags hold its variable.
+    const Plan& sim_plan(uint32_t bundle);
+    const Instr* device_sim_prog(int device, uint32_t bundle, hipStream_t s);
 };
 
 // Device buffers handed out per call (thread-safe pool).
