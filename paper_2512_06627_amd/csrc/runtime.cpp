@@ -239,20 +239,52 @@ bool make_schedule_rows(Device& dev, uint32_t rows, int K, int B, int block, boo
 }
 
 Schedule default_schedule(Device& dev, const std::vector<Circuit*>& cs, const fastlec_es_options* o) {
+    const bool fix_k = o && o->words_per_thread, fix_block = o && o->wg_size;
+    const int K0 = fix_k ? (int)o->words_per_thread : 2;
+    const int block0 = fix_block ? (int)o->wg_size : 256;
+    const bool hbm = o && o->kernel == FASTLEC_KERNEL_INTERP_HBM;
+    if (K0 != 1 && K0 != 2 && K0 != 4) throw Error{kErrInvalid, "words_per_thread must be 1, 2 or 4"};
+    if (block0 < 64 || block0 > 1024 || block0 % 64) throw Error{kErrInvalid, "wg_size must be a multiple of 64 in [64, 1024]"};
+    Schedule s;
+    if (!hbm) {
+        // Value files in LDS: the interpreter is latency-bound, so take the words per lane and
+        // workgroup size that keep the most pattern words in flight per CU (waves x K), with
+        // bundles of 16 gates (8 with four words per lane, which spills registers).  Small
+        // workgroups pack LDS more finely: 164 rows at one word per lane fit three one-wave
+        // workgroups per CU but one two-wave workgroup.
+        bool have = false;
+        int best = -1;
+        for (int K : fix_k ? std::vector<int>{K0} : std::vector<int>{1, 2})
+            for (int block : fix_block ? std::vector<int>{block0} : std::vector<int>{256, 128, 64}) {
+                Schedule t;
+                if (!make_schedule(dev, cs, K, K <= 2 ? 16 : 8, block, true, t)) continue;
+                const int score = t.grid / std::max(1, dev.prop.multiProcessorCount) * (block / 64) * K;
+                if (!have || score > best) {
+                    have = true;
+                    best = score;
+                    s = t;
+                }
+            }
+        if (have) return s;
+    }
+    // Value files in device memory.
+    make_schedule(dev, cs, K0, 8, block0, false, s);
+    return s;
+}
+
+Schedule shrink_schedule(Device& dev, const std::vector<Circuit*>& cs, const fastlec_es_options* o, int B) {
     int K = (o && o->words_per_thread) ? (int)o->words_per_thread : 2;
     int block = (o && o->wg_size) ? (int)o->wg_size : 256;
     bool lds = !(o && o->kernel == FASTLEC_KERNEL_INTERP_HBM);
     if (K != 1 && K != 2 && K != 4) throw Error{kErrInvalid, "words_per_thread must be 1, 2 or 4"};
     if (block < 64 || block > 1024 || block % 64) throw Error{kErrInvalid, "wg_size must be a multiple of 64 in [64, 1024]"};
     Schedule s;
-    // Shrink the workgroup, then K, until one workgroup's value files fit in LDS; else use
-    // value files in device memory.
-    while (lds && !make_schedule(dev, cs, K, 8, block, true, s)) {
+    while (lds && !make_schedule(dev, cs, K, B, block, true, s)) {
         if (!(o && o->wg_size) && block > 64) block /= 2;
         else if (!(o && o->words_per_thread) && K > 1) K /= 2;
         else lds = false;
     }
-    if (!lds) make_schedule(dev, cs, K, 8, block, false, s);
+    if (!lds) make_schedule(dev, cs, K, B, block, false, s);
     return s;
 }
 

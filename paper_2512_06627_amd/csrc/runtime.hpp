@@ -143,6 +143,9 @@ void run_interp(Device& dev, const std::vector<Circuit*>& cs, const std::vector<
                 double* kernel_ms);
 
 Schedule default_schedule(Device& dev, const std::vector<Circuit*>& cs, const fastlec_es_options* o);
+// The server's rule: bundles of B, the option's K (default 2) and workgroup (default 256),
+// shrinking the workgroup and then K only until one workgroup's value files fit in LDS.
+Schedule shrink_schedule(Device& dev, const std::vector<Circuit*>& cs, const fastlec_es_options* o, int B);
 // Schedule for fixed K (half-words per lane), B (bundle) and workgroup size; lds = prefer LDS
 // value files.  Returns false when that combination does not fit (LDS too small).
 bool make_schedule(Device& dev, const std::vector<Circuit*>& cs, int K, int B, int block, bool lds, Schedule& out);

@@ -267,8 +267,7 @@ void fastlec_es_server::step(const std::vector<Job*>& act) {
         fastlec_es_options o = opts;
         o.kernel = g.lds ? FASTLEC_KERNEL_INTERP : FASTLEC_KERNEL_INTERP_HBM;
         o.words_per_thread = kK;
-        g.sch = default_schedule(*dev, *g.c, &o);
-        g.sch.B = kB;
+        g.sch = shrink_schedule(*dev, *g.c, &o, kB);
         g.items = build_descs(*dev, *g.c, *g.r, *g.i, g.sch, stream, (ConeDesc*)(host + g.desc_off));
         if (!g.sch.lds) {
             const size_t need = (size_t)g.sch.grid * (g.sch.block / 64) * rows_for(*g.c, kB) * 64ull * g.sch.K * 4ull;
