@@ -399,18 +399,18 @@ void run_interp(Device& dev, const std::vector<Circuit*>& cs, const std::vector<
 
 namespace fes {
 
-// Fitted on one MI355X: median relative error 8% (interpreter), 16% (specialized), 1%
-// (compile); largest 47%, 61%, 9%.
+// Fitted on one MI355X: median relative error 8% (interpreter), 14% (specialized), 2%
+// (compile); largest 34%, 61%, 11%.
 namespace model {
-constexpr double kInterpT0Ms = 0.0145;
-constexpr uint32_t kInterpSlotsBreak = 140;     // rate drops above: fewer workgroups per CU
-constexpr double kInterpRate = 4.10e13;         // node*patterns/s, value files of <= break slots
-constexpr double kInterpRateLarge = 1.90e13;    // above
-constexpr double kInterpMsPerGateFloor = 5.6e-5; // one wave pass per gate: spaces below a chip's waves
-constexpr double kSpecT0Ms = 0.0132;
-constexpr double kSpecLutPassesPerS = 6.33e11;
-constexpr double kCompileC0Ms = 104.8;
-constexpr double kCompileMsPerLut = 0.00644;
+constexpr double kInterpT0Ms = 0.0182;
+constexpr uint32_t kInterpSlotsBreak = 140;     // rate drops above: fewer waves per CU
+constexpr double kInterpRate = 5.33e13;         // node*patterns/s, value files of <= break slots
+constexpr double kInterpRateLarge = 3.18e13;    // above
+constexpr double kInterpMsPerGateFloor = 4.0e-5; // one wave pass per gate: spaces below a chip's waves
+constexpr double kSpecT0Ms = 0.0128;
+constexpr double kSpecLutPassesPerS = 6.25e11;
+constexpr double kCompileC0Ms = 107.0;
+constexpr double kCompileMsPerLut = 0.00655;
 }  // namespace model
 
 double model_interp_ms(uint32_t gates, uint32_t slots, double patterns) {
