@@ -124,12 +124,14 @@ int fastlec_es_check(const fastlec_es_circuit *c, const fastlec_es_options *opts
  * option's word range is ignored).  With kernel AUTO, circuits that the runtime model
  * (fastlec_es_predict) gives to the specialized kernel are compiled together (up to 64 kernels
  * per hipRTC program) and run as their own launches (kernel_ms their own, compile_ms their
- * share of their program's compile).  The others are grouped
- * by value-file size (powers of two of the row count); each group is one persistent
- * interpreter launch over all its cones, in longest-processing-time order, with a tuned
- * schedule (or the option's schedule fields) and recorded once as a hipGraph; their kernel_ms
- * is the sum over the groups.  cs: k handles; out: k results.  Returns the first per-circuit
- * error; per-circuit errors also appear as a negative verdict. */
+ * share of their program's compile).  Of the others, those predicted to take at least 1 ms on
+ * the interpreter run as their own launches with their own schedule (unless the options fix
+ * words_per_thread or wg_size); the rest are grouped by value-file size (powers of two of the
+ * row count); each group is one persistent interpreter launch over all its cones, in
+ * longest-processing-time order, with a tuned schedule (or the option's schedule fields) and
+ * recorded once as a hipGraph; their kernel_ms is the sum over the groups.  cs: k handles;
+ * out: k results.  Returns the first per-circuit error; per-circuit errors also appear as a
+ * negative verdict. */
 int fastlec_es_check_batch(const fastlec_es_circuit *const *cs, size_t k, const fastlec_es_options *opts,
                            fastlec_es_result *out);
 

@@ -258,13 +258,28 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
                 spec.swap(kept);
             }
         }
+        // Interpreter cones predicted to take at least a millisecond gain nothing from sharing
+        // a launch (a launch costs tens of microseconds) and lose their own schedule to the
+        // group's, which is sized for the group's largest cone: they run as their own launches.
+        std::vector<size_t> alone;
+        std::vector<uint8_t> is_alone(k, 0);
+        if (!o.words_per_thread && !o.wg_size)
+            for (size_t i = 0; i < k; ++i) {
+                if (is_spec[i]) continue;
+                Circuit& c = *v[i];
+                const double patterns = 32.0 * (double)(rs[i].end - rs[i].begin);
+                if (model_interp_ms(std::max<uint32_t>(1, c.plan1.num_gate_instrs), c.plan1.peak_slots, patterns) >= 1.0) {
+                    is_alone[i] = 1;
+                    alone.push_back(i);
+                }
+            }
         // Groups by value-file size: one launch sizes every wave's file for its largest cone,
         // so cones with few rows would otherwise run at the occupancy of the largest.  Rows
         // are bucketed by powers of two; each group gets its own schedule and recorded launch,
         // and the groups run back to back on the stream.
         std::map<uint32_t, std::vector<size_t>> groups;
         for (size_t i = 0; i < k; ++i) {
-            if (is_spec[i]) continue;
+            if (is_spec[i] || is_alone[i]) continue;
             uint32_t rows = v[i]->plan_for(8).rows, b = 0;
             while (rows > 1) {
                 rows >>= 1;
@@ -296,7 +311,19 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
             }
         }
         for (size_t i = 0; i < k; ++i)
-            if (!is_spec[i]) out[i].kernel_ms = total_ms;
+            if (!is_spec[i] && !is_alone[i]) out[i].kernel_ms = total_ms;
+        for (size_t i : alone) {
+            std::vector<Circuit*> one{v[i]};
+            std::vector<HwRange> r1{rs[i]};
+            Schedule sch = default_schedule(dev, one, &o);
+            if (o.tile_words) sch.tile_hw = 2ull * o.tile_words;
+            std::vector<uint64_t> best;
+            double ms = 0;
+            run_interp(dev, one, r1, sch, stream, nullptr, best, &ms);
+            std::memset(&out[i], 0, sizeof(out[i]));
+            fill_result(*v[i], rs[i], best[0], &out[i]);
+            out[i].kernel_ms = ms;
+        }
         if (!spec.empty()) {
             std::vector<Circuit*> sc;
             for (size_t i : spec) sc.push_back(v[i]);

@@ -75,3 +75,26 @@ def test_kernels_compiled_together_give_oracle_answers():
         assert (r["verdict"] == E.FASTLEC_EQUIVALENT) == (want is None)
         if want is not None:
             assert r["cex"] == want
+
+
+def test_batch_runs_large_interpreter_cones_alone():
+    """With the interpreter forced, cones predicted at 1 ms or more run as their own launches and
+    the rest share grouped launches; every answer equals the cone checked alone (and the
+    oracle's for the small ones), and the large cones report their own kernel times."""
+    E = es()
+    small = [miters.layered_cone_miter(120 + i, 12 + i % 5, 400, fault_seed=(i if i % 2 else None)) for i in range(6)]
+    large = [miters.layered_cone_miter(130 + i, 25 + i % 2, 3000, fault_seed=(7 if i == 1 else None)) for i in range(3)]
+    gs = small + large
+    cs = [E.fastlec_es_load_aig(g.to_aig()) for g in gs]
+    preds = [E.fastlec_es_predict(c)["interp_ms"] for c in cs]
+    assert all(p < 1.0 for p in preds[:6]) and all(p >= 1.0 for p in preds[6:])
+    res = E.fastlec_es_check_batch(cs, kernel="interp")
+    for g, c, r in zip(gs, cs, res):
+        alone = E.fastlec_es_check(c, kernel="interp")
+        assert (r["verdict"], r["cex"]) == (alone["verdict"], alone["cex"])
+        if g.num_inputs <= 16:
+            want = oracle.check(g.to_aag(), threads=16)
+            assert (r["cex"] if r["verdict"] else None) == want
+    grouped_ms = {r["kernel_ms"] for r in res[:6]}
+    assert len(grouped_ms) == 1                      # one sum over the grouped launches
+    assert all(r["kernel_ms"] not in grouped_ms for r in res[6:])
