@@ -427,26 +427,36 @@ double model_compile_ms(uint32_t lut_steps) { return model::kCompileC0Ms + model
 void run_sim(Device& dev, Circuit& c, const uint32_t* pi, uint64_t words, uint32_t* sig,
              const fastlec_es_options* o, hipStream_t stream, double* kernel_ms) {
     // Bundles of 16 gates give each wave twice the independent LDS reads per wait (not with 4
-    // words per lane, which spills registers), and one word per lane leaves room for more
-    // waves: 16x16 miter, 2^18 words: 2.96 ms with 8-gate bundles and two words per lane,
-    // 2.37 ms with 16 and one.
-    int K = (o && o->words_per_thread) ? (int)o->words_per_thread : 1;
+    // words per lane, which spills registers).  Words per lane and workgroup size as for plain
+    // checks: the most pattern words in flight per CU (16x16 miter, 2^18 words: 2.96 ms with
+    // 8-gate bundles, two words per lane and the largest workgroup that fits; 2.30 ms with 16,
+    // one and 64 threads).
+    const bool fix_k = o && o->words_per_thread, fix_block = o && o->wg_size;
+    const int K0 = fix_k ? (int)o->words_per_thread : 1;
+    const int block0 = fix_block ? (int)o->wg_size : 256;
+    if (K0 != 1 && K0 != 2 && K0 != 4) throw Error{kErrInvalid, "words_per_thread must be 1, 2 or 4"};
+    if (block0 < 64 || block0 > 1024 || block0 % 64) throw Error{kErrInvalid, "wg_size must be a multiple of 64 in [64, 1024]"};
     const char* eb = std::getenv("FASTLEC_ES_SIM_BUNDLE");
-    const uint32_t B = K == 4 || (eb && std::atoi(eb) == 8) ? 8u : 16u;
+    const uint32_t B = K0 == 4 || (eb && std::atoi(eb) == 8) ? 8u : 16u;
     const Plan& p = c.sim_plan(B);
-    // Schedule as a plain check would pick it (workgroup, then words per lane, shrink until a
-    // workgroup's value files fit in LDS; else value files in device memory), for this plan's rows.
-    int block = (o && o->wg_size) ? (int)o->wg_size : 256;
-    bool lds = !(o && o->kernel == FASTLEC_KERNEL_INTERP_HBM);
-    if (K != 1 && K != 2 && K != 4) throw Error{kErrInvalid, "words_per_thread must be 1, 2 or 4"};
-    if (block < 64 || block > 1024 || block % 64) throw Error{kErrInvalid, "wg_size must be a multiple of 64 in [64, 1024]"};
     Schedule sch;
-    while (lds && !make_schedule_rows(dev, p.rows, K, (int)B, block, true, sch)) {
-        if (!(o && o->wg_size) && block > 64) block /= 2;
-        else if (!(o && o->words_per_thread) && K > 1) K /= 2;
-        else lds = false;
+    bool have = false;
+    if (!(o && o->kernel == FASTLEC_KERNEL_INTERP_HBM)) {
+        int best = -1;
+        for (int K : fix_k ? std::vector<int>{K0} : std::vector<int>{1, 2})
+            for (int block : fix_block ? std::vector<int>{block0} : std::vector<int>{256, 128, 64}) {
+                Schedule t;
+                if (!make_schedule_rows(dev, p.rows, K, (int)B, block, true, t)) continue;
+                const int score = t.grid / std::max(1, dev.prop.multiProcessorCount) * (block / 64) * K;
+                // ties go to the smaller workgroup (one-wave workgroups measured best here)
+                if (!have || score > best || (score == best && K == sch.K)) {
+                    have = true;
+                    best = score;
+                    sch = t;
+                }
+            }
     }
-    if (!lds) make_schedule_rows(dev, p.rows, K, (int)B, block, false, sch);
+    if (!have) make_schedule_rows(dev, p.rows, K0, (int)B, block0, false, sch);
 
     const size_t waves = (size_t)sch.grid * (sch.block / 64);
     const size_t file_bytes = sch.lds ? 0 : waves * p.rows * 64ull * sch.K * 4ull;
