@@ -259,7 +259,7 @@ Schedule default_schedule(Device& dev, const std::vector<Circuit*>& cs, const fa
                 Schedule t;
                 if (!make_schedule(dev, cs, K, K <= 2 ? 16 : 8, block, true, t)) continue;
                 const int score = t.grid / std::max(1, dev.prop.multiProcessorCount) * (block / 64) * K;
-                if (!have || score > best) {
+                if (!have || score > best || (score == best && K == s.K)) {  // ties: smaller workgroup
                     have = true;
                     best = score;
                     s = t;
