@@ -388,11 +388,13 @@ def main():
     if not a.no_secondary:
         sec = {}
         mac = es.fastlec_es_load_aig(miters.workload("mac8_fused_separate").to_aig())
-        es.fastlec_es_check(mac, stream=stream, kernel=a.kernel)
-        r = es.fastlec_es_check(mac, stream=stream, kernel=a.kernel)
+        for _ in range(3):  # compile, then let the clocks settle after the host-side compile
+            es.fastlec_es_check(mac, stream=stream, kernel=a.kernel)
+        rs = [es.fastlec_es_check(mac, stream=stream, kernel=a.kernel) for _ in range(5)]
+        mac_ms = sorted(r["kernel_ms"] for r in rs)[2]
         mi = mac.info()
-        sec["mac8"] = {"kernel_ms": r["kernel_ms"], "equivalent": r["verdict"] == es.FASTLEC_EQUIVALENT,
-                       "node_patterns_per_s": mi["num_ands_tfi"] * (1 << mi["num_pis"]) / (r["kernel_ms"] / 1e3)}
+        sec["mac8"] = {"kernel_ms": mac_ms, "equivalent": all(r["verdict"] == es.FASTLEC_EQUIVALENT for r in rs),
+                       "node_patterns_per_s": mi["num_ands_tfi"] * (1 << mi["num_pis"]) / (mac_ms / 1e3)}
         print(json.dumps({"progress": "mac8", **sec["mac8"]}), file=sys.stderr, flush=True)
         sec["batch"] = batch_leg(es, stream)
         print(json.dumps({"progress": "batch", **sec["batch"]}), file=sys.stderr, flush=True)
