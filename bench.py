@@ -292,8 +292,8 @@ def serve_leg(es, stream, seed: int = 5, seconds: float = 30.0, max_requests: in
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)  # the first includes the compile; then clocks settle
     ap.add_argument("--kernel", default="specialized")
     ap.add_argument("--workload", default="mult16_array_booth")
     ap.add_argument("--no-cpu", action="store_true")
