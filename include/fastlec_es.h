@@ -203,14 +203,17 @@ void fastlec_es_server_destroy(fastlec_es_server *s);
  *             wg_size and kernel (FASTLEC_KERNEL_INTERP_HBM forces value files in device memory)
  *             are honoured; may be NULL.
  *   kernel_ms if not NULL, the kernel's time (HIP events on the launch stream).
- * Blocks until sig is written.  FASTLEC_ERR_INVALID for null pointers or num_words = 0.
+ * Runs on the option's stream (or the library's own stream): the caller's device buffers must
+ * be ready in that stream's order, so pass the stream that produced them (e.g. torch's current
+ * stream for tensors torch just filled).  Blocks until sig is written.  FASTLEC_ERR_INVALID for
+ * null pointers or num_words = 0.
  *
  * fastlec_es_signature_hash: per row r of a signature matrix (device, rows x num_words,
  *   row-major): ones[r] = number of 1 bits; hash[r] = sum over words k of
  *   word'_k * (fmix32(k mod 2^32) | 1) mod 2^64, where word' is the row complemented when
  *   bit 0 of its word 0 is 1 (so a node and its complement hash alike) and fmix32 is the
  *   MurmurHash3 32-bit finaliser.  hash and ones: device pointers, rows entries each,
- *   caller-owned.  Blocks until written.
+ *   caller-owned.  Same stream rule as fastlec_es_simulate.  Blocks until written.
  *
  * fastlec_es_classes: host arrays.  class_of[r] = the lowest row whose hash equals hash[r]
  *   (the class representative; a row is PE with its representative, with complement

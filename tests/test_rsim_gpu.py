@@ -36,7 +36,9 @@ def gpu_sim(aag: bytes, words: np.ndarray, **opts):
     V = info["num_pis"] + info["num_ands"]
     pi = torch.from_numpy(words.view(np.int32).copy()).cuda() if n else None
     sig = torch.full((V + 1, W), -1, dtype=torch.int32, device="cuda")
-    ms = E.fastlec_es_simulate(c, pi, W, sig, **opts)
+    # torch filled the buffers on its current stream: run on that stream, so the library's
+    # kernels are ordered after the fills (another stream could overtake them)
+    ms = E.fastlec_es_simulate(c, pi, W, sig, stream=torch.cuda.current_stream(), **opts)
     assert ms >= 0
     return sig, c
 
@@ -46,7 +48,7 @@ def gpu_hash(sig):
     rows, W = sig.shape
     h = torch.zeros(rows, dtype=torch.int64, device="cuda")
     ones = torch.zeros(rows, dtype=torch.int64, device="cuda")
-    E.fastlec_es_signature_hash(sig, rows, W, h, ones)
+    E.fastlec_es_signature_hash(sig, rows, W, h, ones, stream=torch.cuda.current_stream())
     return h.cpu().numpy().view(np.uint64), ones.cpu().numpy().view(np.uint64)
 
 
@@ -140,7 +142,8 @@ def test_repeated_calls_reuse_cached_program():
     for W in (500, 77):
         w = words[:, :W].copy()
         sig = torch.zeros((V + 1, W), dtype=torch.int32, device="cuda")
-        es().fastlec_es_simulate(c, torch.from_numpy(w.view(np.int32)).cuda(), W, sig)
+        es().fastlec_es_simulate(c, torch.from_numpy(w.view(np.int32)).cuda(), W, sig,
+                                 stream=torch.cuda.current_stream())
         assert np.array_equal(sig.cpu().numpy().view(np.uint32), rsim.simulate(g.to_aag(), w))
 
 

@@ -44,10 +44,11 @@ def gpu_classes(g, words):
     n, W = words.shape
     V = info["num_pis"] + info["num_ands"]
     sig = torch.empty((V + 1, W), dtype=torch.int32, device="cuda")
-    E.fastlec_es_simulate(c, torch.from_numpy(words.view(np.int32).copy()).cuda(), W, sig)
+    st = torch.cuda.current_stream()  # the stream torch fills its buffers on
+    E.fastlec_es_simulate(c, torch.from_numpy(words.view(np.int32).copy()).cuda(), W, sig, stream=st)
     h = torch.empty(V + 1, dtype=torch.int64, device="cuda")
     ones = torch.empty(V + 1, dtype=torch.int64, device="cuda")
-    E.fastlec_es_signature_hash(sig, V + 1, W, h, ones)
+    E.fastlec_es_signature_hash(sig, V + 1, W, h, ones, stream=st)
     cls = E.fastlec_es_classes(h.cpu().numpy().view(np.uint64))
     pol = (sig[:, 0] & 1).to(torch.uint8).cpu().numpy()
     return c, cls, pol
