@@ -68,7 +68,8 @@ typedef struct {
     uint32_t peak_live_slots;  /* S: node values alive at once under the planned order */
     uint32_t num_instrs;       /* interpreter instructions (N plus output-only instructions) */
     uint32_t levels;           /* logic depth of the cone */
-    uint32_t reserved;
+    uint32_t num_xors;         /* three-AND XORs (x&y, ~x&~y, ~t1&~t2, inner gates read once) that the
+                                  interpreter's bundled streams run as one XOR instruction each */
 } fastlec_es_info;
 
 typedef struct {
@@ -261,10 +262,11 @@ int fastlec_es_submiter_aag(const fastlec_es_circuit *c, const uint32_t *class_o
 /* Predicted kernel times of a plain check of c over [begin_word, end_word) (0, 0 = the whole
  * space), by the paper's runtime form (linear in gates, exponential in inputs; Section 3.2,
  * runtime prediction) fitted per kernel on MI355X with a fixed launch cost:
- *   interp_ms       t0 + N * max(patterns / R, L); R depends on the value-file size (S)
+ *   interp_ms       t0 + N * max(patterns / R, L); N = gate instructions of the bundled stream
+ *                   (num_instrs - 2 * num_xors); R depends on the value-file size (S)
  *   specialized_ms  t0 + (LUT steps) * max(1, patterns / 2048) / R
  *   compile_ms      hipRTC compile of the specialized kernel: c0 + c1 * (LUT steps)
- * Median errors on the fitting set: 8%, 14%, 2%.  Outputs may be NULL; asking for
+ * Median errors on the fitting set: 9%, 15%, 1%.  Outputs may be NULL; asking for
  * specialized_ms or compile_ms builds the circuit's LUT program (host time).  The AUTO kernel
  * choice of fastlec_es_check uses the same model. */
 int fastlec_es_predict(const fastlec_es_circuit *c, uint64_t begin_word, uint64_t end_word, double *interp_ms,

@@ -7,7 +7,8 @@ together are one rate, since alpha * 2^-beta is a single constant).  The
 library's model (fastlec_es_predict) keeps that form per kernel and adds a
 fixed launch cost:
 
-* interpreter: t = t0 + N * max(2^n / R, L), N = AND gates in the cone, with one rate R
+* interpreter: t = t0 + N * max(2^n / R, L), N = gate instructions of its stream (AND gates
+  of the cone, each fused three-AND XOR counted once), with one rate R
   for value files of at most ROWS_BREAK rows and another above (the workgroups a CU holds
   halve there, and the interpreter is latency-bound); L is the time per gate of one wave's
   pass, the floor when the space has fewer passes than the chip has waves;
@@ -51,7 +52,8 @@ def measure(es, stream, reps=3):
     for name, g in cones():
         c = es.fastlec_es_load_aig(g.to_aig())
         info = c.info()
-        rec = {"name": name, "n": info["num_pis"], "N": info["num_ands_tfi"], "rows": info["peak_live_slots"],
+        rec = {"name": name, "n": info["num_pis"], "N": info["num_instrs"] - 2 * info["num_xors"],
+               "rows": info["peak_live_slots"],
                "luts": lut_steps(es, c)}
         if rec["N"] * (1 << rec["n"]) <= 3e12:
             es.fastlec_es_check(c, stream=stream, kernel="interp")

@@ -18,6 +18,10 @@ struct Aig {
     std::vector<uint32_t> and_r0;  // fanin literals of AND k (var num_inputs + 1 + k)
     std::vector<uint32_t> and_r1;
     std::vector<uint32_t> outputs; // output literals
+    // Nonzero entry k: gate k computes lit(and_r0[k]) XOR lit(and_r1[k]) instead of the AND
+    // (interpreter plans of a fused copy only; empty = every gate is an AND).
+    std::vector<uint8_t> xor_gate;
+    bool is_xor(uint32_t k) const { return k < xor_gate.size() && xor_gate[k]; }
     uint32_t num_ands() const { return (uint32_t)and_r0.size(); }
     uint32_t max_var() const { return num_inputs + num_ands(); }
 };

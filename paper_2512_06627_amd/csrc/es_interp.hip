@@ -170,8 +170,18 @@ __global__ void __launch_bounds__(1024) es_interp_kernel(InterpLaunch L) {
                 for (int u = 0; u < B; ++u) {
                     const uint32_t ca = 0u - (ins[u].a >> 31), cb = 0u - (ins[u].b >> 31);
                     V r;
+                    if constexpr (kSim) {
 #pragma unroll
-                    for (int j = 0; j < K; ++j) r.w[j] = (a[u].w[j] ^ ca) & (b[u].w[j] ^ cb);
+                        for (int j = 0; j < K; ++j) r.w[j] = (a[u].w[j] ^ ca) & (b[u].w[j] ^ cb);
+                    } else {
+                        // XOR instructions (three fused ANDs): all-ones mask selects a ^ b
+                        const uint32_t xm = 0u - ((ins[u].flags >> 2) & 1u);
+#pragma unroll
+                        for (int j = 0; j < K; ++j) {
+                            const uint32_t x = a[u].w[j] ^ ca, y = b[u].w[j] ^ cb;
+                            r.w[j] = ((x & y) & ~xm) | ((x ^ y) & xm);
+                        }
+                    }
                     *(V*)(col + (size_t)ins[u].d * kRowWords) = r;
                     if constexpr (kSim) {
                         if (ins[u].flags) {
@@ -181,7 +191,7 @@ __global__ void __launch_bounds__(1024) es_interp_kernel(InterpLaunch L) {
                                 if (w < W) L.sim_sig[(size_t)ins[u].flags * W + w] = r.w[j];
                             }
                         }
-                    } else if (ins[u].flags) {
+                    } else if (ins[u].flags & (kOutPos | kOutNeg)) {
                         const uint32_t op = 0u - (ins[u].flags & kOutPos), on = 0u - ((ins[u].flags >> 1) & 1u);
 #pragma unroll
                         for (int j = 0; j < K; ++j) m.w[j] |= (r.w[j] & op) | (~r.w[j] & on);

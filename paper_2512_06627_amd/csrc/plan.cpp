@@ -168,7 +168,7 @@ Alloc allocate(const Aig& g, const std::vector<std::vector<uint32_t>>& bundles, 
             }
             Instr& ins = al.prog[first + t];
             ins.d = n + 1 + slot[v];
-            ins.flags = (pos_refs[v] ? kOutPos : 0u) | (neg_refs[v] ? kOutNeg : 0u);
+            ins.flags = (pos_refs[v] ? kOutPos : 0u) | (neg_refs[v] ? kOutNeg : 0u) | (g.is_xor(b[t]) ? kXor : 0u);
         }
         for (uint32_t k : b) {
             uint32_t v = n + 1 + k;
@@ -197,6 +197,36 @@ Alloc allocate(const Aig& g, const std::vector<std::vector<uint32_t>>& bundles, 
 }
 
 }  // namespace
+
+Aig fuse_xors(const Aig& g) {
+    const uint32_t A = g.num_ands();
+    std::vector<uint32_t> readers(g.max_var() + 1, 0);
+    for (uint32_t k = 0; k < A; ++k) {
+        ++readers[g.and_r0[k] >> 1];
+        ++readers[g.and_r1[k] >> 1];
+    }
+    for (uint32_t o : g.outputs) ++readers[o >> 1];
+    Aig f = g;
+    f.xor_gate.assign(A, 0);
+    std::vector<uint8_t> absorbed(A, 0);
+    for (uint32_t k = 0; k < A; ++k) {
+        const uint32_t l1 = g.and_r0[k], l2 = g.and_r1[k];
+        if (!(l1 & 1) || !(l2 & 1)) continue;  // both fanins complemented
+        const uint32_t t1 = l1 >> 1, t2 = l2 >> 1;
+        if (t1 == t2 || !is_and(g, t1) || !is_and(g, t2) || readers[t1] != 1 || readers[t2] != 1) continue;
+        const uint32_t k1 = and_index(g, t1), k2 = and_index(g, t2);
+        if (f.xor_gate[k1] || f.xor_gate[k2] || absorbed[k1] || absorbed[k2]) continue;
+        const uint32_t x = g.and_r0[k1], y = g.and_r1[k1];
+        const uint32_t p = g.and_r0[k2], q = g.and_r1[k2];
+        if (!((p == (x ^ 1u) && q == (y ^ 1u)) || (p == (y ^ 1u) && q == (x ^ 1u)))) continue;
+        if ((x >> 1) == (y >> 1)) continue;  // x & ~x: leave constant gates to the AND path
+        f.and_r0[k] = x;
+        f.and_r1[k] = y;
+        f.xor_gate[k] = 1;
+        absorbed[k1] = absorbed[k2] = 1;
+    }
+    return f;
+}
 
 Plan make_plan(const Aig& g, Order order, uint32_t bundle) {
     if (bundle == 0) bundle = 1;
@@ -300,7 +330,8 @@ std::string validate_plan(const Aig& g, const Plan& p) {
                 continue;
             }
             for (uint32_t k : by_fanin0[s.la >> 1])
-                if (!done[k] && in_cone[k] && g.and_r0[k] == s.la && g.and_r1[k] == s.lb) {
+                if (!done[k] && in_cone[k] && g.and_r0[k] == s.la && g.and_r1[k] == s.lb &&
+                    ((ins.flags & kXor) != 0) == g.is_xor(k)) {
                     bool taken = false;
                     for (auto& o : steps) taken |= o.gate == (int64_t)k;
                     if (!taken) { s.gate = k; break; }
@@ -330,7 +361,7 @@ std::string validate_plan(const Aig& g, const Plan& p) {
                     want |= (o & 1) ? kOutNeg : kOutPos;
                     --reads[v];
                 }
-            if (s.flags != want) return "output flags wrong";
+            if ((s.flags & ~kXor) != want) return "output flags wrong";
         }
     }
     for (uint32_t k = 0; k < g.num_ands(); ++k)

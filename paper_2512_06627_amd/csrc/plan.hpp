@@ -24,11 +24,11 @@ struct Instr {
     uint32_t a;      // row of fanin 0; bit 31 = complement
     uint32_t b;      // row of fanin 1; bit 31 = complement
     uint32_t d;      // destination row
-    uint32_t flags;  // kOutPos: miter |= value; kOutNeg: miter |= ~value
+    uint32_t flags;  // kOutPos: miter |= value; kOutNeg: miter |= ~value; kXor: a XOR b, not a AND b
 };
 static_assert(sizeof(Instr) == 16, "instruction must stay 16 bytes");
 
-enum : uint32_t { kCompl = 0x80000000u, kRowMask = 0x7FFFFFFFu, kOutPos = 1u, kOutNeg = 2u };
+enum : uint32_t { kCompl = 0x80000000u, kRowMask = 0x7FFFFFFFu, kOutPos = 1u, kOutNeg = 2u, kXor = 4u };
 
 enum class Order : int { Auto = 0, DfsLabel = 1, DfsFanin0 = 2, File = 3 };
 
@@ -50,6 +50,12 @@ struct Plan {
     std::vector<uint32_t> instr_gate;  // per prog entry: the AND gate it computes, or UINT32_MAX
                                        // (output-only step or padding)
 };
+
+// XOR fusion for interpreter plans (the three-AND XOR as one instruction): a gate
+// v = ~t1 & ~t2 with t1 = x & y and t2 = ~x & ~y, where t1 and t2 have no other reader,
+// equals x XOR y.  The copy keeps every variable's number; v becomes an XOR gate over
+// (x, y), and t1, t2 drop out of the output cone.
+Aig fuse_xors(const Aig& g);
 
 // bundle = 1: sequential stream.  bundle > 1: list-scheduled so that the gates of a
 // bundle do not read each other, keeping the chosen order as the priority.

@@ -64,7 +64,7 @@ const Plan& Circuit::plan_for(uint32_t bundle) {
     if (bundle <= 1) return plan1;
     std::lock_guard<std::mutex> g(mu);
     auto it = bundled.find(bundle);
-    if (it == bundled.end()) it = bundled.emplace(bundle, std::make_unique<Plan>(make_plan(aig, Order::Auto, bundle))).first;
+    if (it == bundled.end()) it = bundled.emplace(bundle, std::make_unique<Plan>(make_plan(fused, Order::Auto, bundle))).first;
     return *it->second;
 }
 
@@ -399,18 +399,19 @@ void run_interp(Device& dev, const std::vector<Circuit*>& cs, const std::vector<
 
 namespace fes {
 
-// Fitted on one MI355X: median relative error 8% (interpreter), 14% (specialized), 2%
-// (compile); largest 34%, 61%, 11%.
+// Fitted on one MI355X: median relative error 9% (interpreter), 15% (specialized), 1%
+// (compile); largest 27%, 61%, 4%.  Interpreter gates are the instructions of its bundled
+// stream (three-AND XORs count once).
 namespace model {
-constexpr double kInterpT0Ms = 0.0182;
+constexpr double kInterpT0Ms = 0.0164;
 constexpr uint32_t kInterpSlotsBreak = 140;     // rate drops above: fewer waves per CU
-constexpr double kInterpRate = 5.33e13;         // node*patterns/s, value files of <= break slots
-constexpr double kInterpRateLarge = 3.18e13;    // above
-constexpr double kInterpMsPerGateFloor = 4.0e-5; // one wave pass per gate: spaces below a chip's waves
-constexpr double kSpecT0Ms = 0.0128;
-constexpr double kSpecLutPassesPerS = 6.25e11;
-constexpr double kCompileC0Ms = 107.0;
-constexpr double kCompileMsPerLut = 0.00655;
+constexpr double kInterpRate = 4.29e13;         // gate instructions*patterns/s, value files of <= break slots
+constexpr double kInterpRateLarge = 2.52e13;    // above
+constexpr double kInterpMsPerGateFloor = 5.6e-5; // one wave pass per gate: spaces below a chip's waves
+constexpr double kSpecT0Ms = 0.0129;
+constexpr double kSpecLutPassesPerS = 6.17e11;
+constexpr double kCompileC0Ms = 105.4;
+constexpr double kCompileMsPerLut = 0.00667;
 }  // namespace model
 
 double model_interp_ms(uint32_t gates, uint32_t slots, double patterns) {

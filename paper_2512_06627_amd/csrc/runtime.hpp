@@ -70,6 +70,13 @@ struct Circuit {
     uint64_t uid = 0;  // unique per loaded circuit in this process (never reused)
     Aig aig;
     Plan plan1;  // sequential plan (specialized kernel, info)
+    Aig fused;   // copy with three-AND XORs fused (interpreter plans of bundles > 1)
+    uint32_t fused_xors = 0;  // XOR gates of `fused` in the output cone (each replaces three ANDs)
+    // Gate instructions of a bundled interpreter stream (runtime model's gate count).
+    uint32_t interp_gates() const {
+        const uint32_t g = plan1.num_gate_instrs - 2u * fused_xors;
+        return g ? g : 1u;
+    }
     double plan_ms = 0;
     std::mutex mu;
     std::map<uint32_t, std::unique_ptr<Plan>> bundled;                  // bundle size -> plan

@@ -40,6 +40,12 @@ int main(int argc, char** argv) {
                 std::printf("%d plan %u: %s\n", f - 2, b, err.c_str());
                 return 1;
             }
+            const Aig fused = fuse_xors(g);  // interpreter plans of bundles > 1 use the fused copy
+            const std::string ferr = validate_plan(fused, make_plan(fused, Order::Auto, b));
+            if (!ferr.empty()) {
+                std::printf("%d fused plan %u: %s\n", f - 2, b, ferr.c_str());
+                return 1;
+            }
         }
         std::vector<uint32_t> words;
         for (int policy : {0, 2}) {

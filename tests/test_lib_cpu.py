@@ -193,3 +193,81 @@ def test_specialized_kernels_compile_together():
     assert es.fastlec_es_compile_specialized_many(cs, 3) == 0
     with pytest.raises(es.EsError):
         es.fastlec_es_compile_specialized_many(cs, 0)
+
+
+# ---- three-AND XORs fused into one interpreter instruction ----------------------------------
+
+def _xor_roots(g):
+    """Gates k = ~t1 & ~t2 with t1 = x & y, t2 = ~x & ~y, t1 and t2 read only by k, taken in
+    variable order; a gate already taken as such a root is not the inner gate of another.
+    Counted over the output cone (gates some output depends on)."""
+    n = g.num_inputs
+    cone, stack = set(), [o >> 1 for o in g.outputs]
+    while stack:
+        v = stack.pop()
+        if v > n and v not in cone:
+            cone.add(v)
+            stack.extend(r >> 1 for r in g.ands[v - n - 1])
+    readers = {}
+    for r0, r1 in g.ands:
+        for r in (r0, r1):
+            readers[r >> 1] = readers.get(r >> 1, 0) + 1
+    for o in g.outputs:
+        readers[o >> 1] = readers.get(o >> 1, 0) + 1
+    roots = set()
+    for k, (l1, l2) in enumerate(g.ands):
+        if not (l1 & 1 and l2 & 1):
+            continue
+        t1, t2 = l1 >> 1, l2 >> 1
+        if t1 == t2 or t1 <= n or t2 <= n or readers[t1] != 1 or readers[t2] != 1:
+            continue
+        if (t1 - n - 1) in roots or (t2 - n - 1) in roots:
+            continue
+        x, y = g.ands[t1 - n - 1]
+        p, q = g.ands[t2 - n - 1]
+        if {p, q} == {x ^ 1, y ^ 1} and x >> 1 != y >> 1:
+            roots.add(k)
+    return sum(1 for k in roots if n + 1 + k in cone)
+
+
+def _parity(n, form):
+    from miters.aig import Aig
+    g = Aig(n)
+    acc = g.input(0)
+    for i in range(1, n):
+        acc = getattr(g, form)(acc, g.input(i))
+    g.add_output(acc)
+    return g
+
+
+@pytest.mark.parametrize("form", ["XOR", "XOR_alt", "XOR_andor"])
+def test_xor_fusion_parity_chains(form):
+    """Each of the three common three-AND XOR forms is fused; the bundled streams (which run the
+    fused copy) replay to the oracle's miter words on every pattern."""
+    g = _parity(9, form)
+    c = es.fastlec_es_load_aig(g.to_aig())
+    assert c.info()["num_xors"] == 8 == _xor_roots(g)
+    for bundle in (1, 4, 8, 16):
+        _replay_vs_oracle(g, bundle, range(1 << 4))
+
+
+def test_xor_fusion_skips_shared_inner_gates():
+    """A half adder's carry reads x & y too, so its XOR keeps its three ANDs."""
+    from miters.aig import Aig
+    g = Aig(6)
+    s = g.XOR(g.input(0), g.input(1))
+    carry = g.AND(g.input(0), g.input(1))
+    g.add_output(g.AND(s, g.input(2)))
+    g.add_output(g.AND(carry, g.input(3)))
+    g.add_output(g.XOR(g.input(4), g.input(5)))   # this one is fused
+    c = es.fastlec_es_load_aig(g.to_aig())
+    assert c.info()["num_xors"] == 1 == _xor_roots(g)
+    for bundle in (1, 4, 16):
+        _replay_vs_oracle(g, bundle, range(2))
+
+
+@pytest.mark.parametrize("name", ["mult12_array_booth", "mac8_fused_separate", "mult16_array_booth"])
+def test_xor_fusion_count_matches_definition(name):
+    g = miters.workload(name)
+    c = es.fastlec_es_load_aig(g.to_aig())
+    assert c.info()["num_xors"] == _xor_roots(g) > 0
