@@ -174,12 +174,13 @@ __global__ void __launch_bounds__(1024) es_interp_kernel(InterpLaunch L) {
 #pragma unroll
                         for (int j = 0; j < K; ++j) r.w[j] = (a[u].w[j] ^ ca) & (b[u].w[j] ^ cb);
                     } else {
-                        // XOR instructions (three fused ANDs): all-ones mask selects a ^ b
+                        // XOR instructions (three fused ANDs): the all-ones mask selects x ^ y.
+                        // One v_bitop3 over (x, y, mask); table bit 4x + 2y + m is m ? x ^ y : x & y.
                         const uint32_t xm = 0u - ((ins[u].flags >> 2) & 1u);
 #pragma unroll
                         for (int j = 0; j < K; ++j) {
                             const uint32_t x = a[u].w[j] ^ ca, y = b[u].w[j] ^ cb;
-                            r.w[j] = ((x & y) & ~xm) | ((x ^ y) & xm);
+                            r.w[j] = __builtin_amdgcn_bitop3_b32(x, y, xm, 0x68);
                         }
                     }
                     *(V*)(col + (size_t)ins[u].d * kRowWords) = r;
