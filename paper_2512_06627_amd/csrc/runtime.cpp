@@ -399,19 +399,19 @@ void run_interp(Device& dev, const std::vector<Circuit*>& cs, const std::vector<
 
 namespace fes {
 
-// Fitted on one MI355X: median relative error 9% (interpreter), 15% (specialized), 1%
-// (compile); largest 27%, 61%, 4%.  Interpreter gates are the instructions of its bundled
+// Fitted on one MI355X: median relative error 8% (interpreter), 16% (specialized), 1%
+// (compile); largest 28%, 61%, 4%.  Interpreter gates are the instructions of its bundled
 // stream (three-AND XORs count once).
 namespace model {
-constexpr double kInterpT0Ms = 0.0164;
+constexpr double kInterpT0Ms = 0.0169;
 constexpr uint32_t kInterpSlotsBreak = 140;     // rate drops above: fewer waves per CU
-constexpr double kInterpRate = 4.29e13;         // gate instructions*patterns/s, value files of <= break slots
-constexpr double kInterpRateLarge = 2.52e13;    // above
-constexpr double kInterpMsPerGateFloor = 5.6e-5; // one wave pass per gate: spaces below a chip's waves
-constexpr double kSpecT0Ms = 0.0129;
-constexpr double kSpecLutPassesPerS = 6.17e11;
-constexpr double kCompileC0Ms = 105.4;
-constexpr double kCompileMsPerLut = 0.00667;
+constexpr double kInterpRate = 4.62e13;         // gate instructions*patterns/s, value files of <= break slots
+constexpr double kInterpRateLarge = 2.71e13;    // above
+constexpr double kInterpMsPerGateFloor = 5.0e-5; // one wave pass per gate: spaces below a chip's waves
+constexpr double kSpecT0Ms = 0.0130;
+constexpr double kSpecLutPassesPerS = 6.33e11;
+constexpr double kCompileC0Ms = 104.1;
+constexpr double kCompileMsPerLut = 0.00649;
 }  // namespace model
 
 double model_interp_ms(uint32_t gates, uint32_t slots, double patterns) {
