@@ -170,7 +170,7 @@ void run_batch_graph(Device& dev, const std::vector<Circuit*>& cs, const std::ve
         const size_t file_bytes = sch.lds ? 0 : waves * rows_max * 64ull * sch.K * 4ull;
         nb->best_off = sizeof(LaunchCtl);
         nb->total = files_off + file_bytes;
-        nb->buf = dev.acquire(nb->total);
+        nb->buf = dev.acquire(nb->total, files_off);
         uint8_t* host = (uint8_t*)nb->buf.host;
         uint8_t* devp = (uint8_t*)nb->buf.dev;
         std::memset(host, 0, files_off);

@@ -128,13 +128,18 @@ const Instr* Circuit::device_sim_prog(int dev, uint32_t bundle, hipStream_t s) {
 
 // ---- devices ----------------------------------------------------------------
 
-Buffer Device::acquire(size_t bytes) {
-    bytes = (bytes + 4095) & ~size_t(4095);
+Buffer Device::acquire(size_t dev_bytes, size_t host_bytes) {
+    dev_bytes = (dev_bytes + 4095) & ~size_t(4095);
+    host_bytes = (host_bytes + 4095) & ~size_t(4095);
     {
         std::lock_guard<std::mutex> g(mu);
         size_t best = SIZE_MAX;
-        for (size_t i = 0; i < free_bufs.size(); ++i)
-            if (free_bufs[i].bytes >= bytes && (best == SIZE_MAX || free_bufs[i].bytes < free_bufs[best].bytes)) best = i;
+        for (size_t i = 0; i < free_bufs.size(); ++i) {
+            const Buffer& f = free_bufs[i];
+            if (f.bytes >= dev_bytes && f.host_bytes >= host_bytes &&
+                (best == SIZE_MAX || f.bytes + f.host_bytes < free_bufs[best].bytes + free_bufs[best].host_bytes))
+                best = i;
+        }
         if (best != SIZE_MAX) {
             Buffer b = free_bufs[best];
             free_bufs.erase(free_bufs.begin() + best);
@@ -142,12 +147,16 @@ Buffer Device::acquire(size_t bytes) {
         }
     }
     Buffer b;
-    b.bytes = bytes;
-    if (hipMalloc(&b.dev, bytes) != hipSuccess) throw Error{kErrNoMem, "device allocation failed"};
-    if (hipHostMalloc(&b.host, bytes, hipHostMallocDefault) != hipSuccess) {
+    b.bytes = dev_bytes;
+    b.host_bytes = host_bytes;
+    if (hipMalloc(&b.dev, dev_bytes) != hipSuccess) throw Error{kErrNoMem, "device allocation failed"};
+    if (host_bytes && hipHostMalloc(&b.host, host_bytes, hipHostMallocDefault) != hipSuccess) {
         (void)hipFree(b.dev);
         throw Error{kErrNoMem, "pinned host allocation failed"};
     }
+    std::lock_guard<std::mutex> g(mu);
+    pool_device_bytes += dev_bytes;
+    pool_pinned_bytes += host_bytes;
     return b;
 }
 
@@ -298,8 +307,6 @@ uint64_t build_descs(Device& dev, const std::vector<Circuit*>& cs, const std::ve
                      const std::vector<uint32_t>& best_index, const Schedule& sch, hipStream_t stream,
                      ConeDesc* out) {
     const size_t k = cs.size();
-    const uint32_t pass_hw = 64u * (uint32_t)sch.K;
-    const size_t waves = (size_t)sch.grid * (sch.block / 64);
     // Longest-processing-time order: cones with the most gate evaluations get the lowest
     // item numbers, so the big ones start first and the small ones fill the tail.
     std::vector<size_t> order(k);
@@ -312,30 +319,36 @@ uint64_t build_descs(Device& dev, const std::vector<Circuit*>& cs, const std::ve
     for (size_t t = 0; t < k; ++t) {
         size_t i = order[t];
         Circuit* c = cs[i];
-        const Plan& p = c->plan_for(sch.B);
-        ConeDesc& d = out[t];
-        d.prog = c->device_prog(dev.ordinal, sch.B, stream);
-        d.n_instr = (uint32_t)p.prog.size();
-        d.n_inputs = p.num_inputs;
-        d.rows = p.rows;
-        d.best_index = best_index[i];
-        d.hw_begin = ranges[i].begin;
-        d.hw_end = ranges[i].end;
-        d.hw_first = ranges[i].begin / pass_hw * pass_hw;
-        const uint64_t span = d.hw_end - d.hw_first;
-        uint64_t tile = sch.tile_hw;
-        if (!tile) {  // about 16 work items per wave over the launch, within [1, 64] passes
-            const uint64_t target = span / std::max<uint64_t>(1, waves * 16);
-            tile = pass_hw;
-            while (tile < target && tile < 64ull * pass_hw) tile *= 2;
-        }
-        tile = (tile + pass_hw - 1) / pass_hw * pass_hw;
-        d.tile_hw = tile;
-        d.item_begin = item;
-        item += (span + tile - 1) / tile;
-        d.item_end = item;
+        item = fill_desc(c->plan_for(sch.B), c->device_prog(dev.ordinal, sch.B, stream), ranges[i], best_index[i],
+                         sch, item, out[t]);
     }
     return item;
+}
+
+uint64_t fill_desc(const Plan& p, const Instr* prog, const HwRange& r, uint32_t best_index, const Schedule& sch,
+                   uint64_t item_begin, ConeDesc& d) {
+    const uint32_t pass_hw = 64u * (uint32_t)sch.K;
+    const size_t waves = (size_t)sch.grid * (sch.block / 64);
+    d.prog = prog;
+    d.n_instr = (uint32_t)p.prog.size();
+    d.n_inputs = p.num_inputs;
+    d.rows = p.rows;
+    d.best_index = best_index;
+    d.hw_begin = r.begin;
+    d.hw_end = r.end;
+    d.hw_first = r.begin / pass_hw * pass_hw;
+    const uint64_t span = d.hw_end - d.hw_first;
+    uint64_t tile = sch.tile_hw;
+    if (!tile) {  // about 16 work items per wave over the launch, within [1, 64] passes
+        const uint64_t target = span / std::max<uint64_t>(1, waves * 16);
+        tile = pass_hw;
+        while (tile < target && tile < 64ull * pass_hw) tile *= 2;
+    }
+    tile = (tile + pass_hw - 1) / pass_hw * pass_hw;
+    d.tile_hw = tile;
+    d.item_begin = item_begin;
+    d.item_end = item_begin + (span + tile - 1) / tile;
+    return d.item_end;
 }
 
 void run_interp(Device& dev, const std::vector<Circuit*>& cs, const std::vector<HwRange>& ranges, const Schedule& sch,
@@ -345,7 +358,7 @@ void run_interp(Device& dev, const std::vector<Circuit*>& cs, const std::vector<
     const size_t waves = (size_t)sch.grid * (sch.block / 64);
     const size_t file_bytes = sch.lds ? 0 : waves * rows_max * 64ull * sch.K * 4ull;
     Layout lay = layout(k, file_bytes);
-    Buffer buf = dev.acquire(lay.total);
+    Buffer buf = dev.acquire(lay.total, lay.files_off);
     struct Releaser {
         Device& d;
         Buffer b;
@@ -462,7 +475,7 @@ void run_sim(Device& dev, Circuit& c, const uint32_t* pi, uint64_t words, uint32
     const size_t waves = (size_t)sch.grid * (sch.block / 64);
     const size_t file_bytes = sch.lds ? 0 : waves * p.rows * 64ull * sch.K * 4ull;
     Layout lay = layout(1, file_bytes);
-    Buffer buf = dev.acquire(lay.total);
+    Buffer buf = dev.acquire(lay.total, lay.files_off);
     struct Releaser {
         Device& d;
         Buffer b;

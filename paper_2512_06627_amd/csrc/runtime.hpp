@@ -95,11 +95,14 @@ struct Circuit {
     const Instr* device_sim_prog(int device, uint32_t bundle, hipStream_t s);
 };
 
-// Device buffers handed out per call (thread-safe pool).
+// Device buffers handed out per call (thread-safe pool).  Only the first host_bytes of a
+// buffer are staged through the host (control block, best values, descriptors); device-only
+// parts such as value files have no pinned host copy.
 struct Buffer {
     void* dev = nullptr;
-    void* host = nullptr;  // pinned, same size
-    size_t bytes = 0;
+    void* host = nullptr;   // pinned, host_bytes (null when host_bytes is 0)
+    size_t bytes = 0;       // device bytes
+    size_t host_bytes = 0;
 };
 
 struct Device {
@@ -109,7 +112,9 @@ struct Device {
     hipStream_t capture_stream = nullptr;  // used only to record hipGraphs
     std::mutex mu;
     std::vector<Buffer> free_bufs;
-    Buffer acquire(size_t bytes);
+    size_t pool_device_bytes = 0, pool_pinned_bytes = 0;  // held by the pool (in use or free)
+    Buffer acquire(size_t bytes) { return acquire(bytes, bytes); }
+    Buffer acquire(size_t dev_bytes, size_t host_bytes);
     void release(Buffer b);
 };
 Device& device(int ordinal);
@@ -136,12 +141,18 @@ struct HwRange {
 };
 HwRange range_of(uint32_t n, uint64_t begin_word, uint64_t end_word);
 
+
 // Descriptors of an interpreter launch, written to `out` in longest-processing-time order
 // (most gate evaluations first); cone i reports into best[best_index[i]].  Returns the
 // launch's total number of work items.
 uint64_t build_descs(Device& dev, const std::vector<Circuit*>& cs, const std::vector<HwRange>& ranges,
                      const std::vector<uint32_t>& best_index, const Schedule& sch, hipStream_t stream,
                      ConeDesc* out);
+// One descriptor: cone plan p with its device stream prog over range r, work items numbered
+// from item_begin (tile size from the schedule unless sch.tile_hw fixes it).  Returns the
+// next free item number.
+uint64_t fill_desc(const Plan& p, const Instr* prog, const HwRange& r, uint32_t best_index, const Schedule& sch,
+                   uint64_t item_begin, ConeDesc& d);
 uint32_t rows_for(const std::vector<Circuit*>& cs, int B);
 
 // One interpreter launch over several cones (k = 1 for a plain check).

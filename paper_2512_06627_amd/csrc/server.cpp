@@ -303,7 +303,7 @@ void fastlec_es_server::step(const std::vector<Job*>& act) {
             if (files.bytes < need) {
                 if (files.dev) dev->release(files);
                 files = Buffer{};
-                files = dev->acquire(need);
+                files = dev->acquire(need, 0);  // device-only value files
             }
         }
     }
