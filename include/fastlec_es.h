@@ -136,6 +136,34 @@ int fastlec_es_check(const fastlec_es_circuit *c, const fastlec_es_options *opts
 int fastlec_es_check_batch(const fastlec_es_circuit *const *cs, size_t k, const fastlec_es_options *opts,
                            fastlec_es_result *out);
 
+/* ---- exact simulation without device allocation --------------------------- */
+
+/* Bytes of the library's static device array used by fastlec_es_check_noalloc (one per
+ * device the library runs on, held until the process ends). */
+#define FASTLEC_NOALLOC_SCRATCH_BYTES (1u << 20)
+
+/* For callers that cannot allocate device memory (code that must not call hipMalloc, such as
+ * work recorded under HIP graph capture, tight serving loops, harnesses that forbid it): the
+ * same check as fastlec_es_check with the interpreter kernel and value files in LDS, whose
+ * control block, best value, descriptor and a copy of the circuit's instruction stream live
+ * in a static device array of FASTLEC_NOALLOC_SCRATCH_BYTES bytes instead of library
+ * allocations.  It calls no hipMalloc, hipFree, hipHostMalloc or event creation; it copies
+ * from pageable host memory and waits on the stream.  The first library call on a device
+ * (any entry point) sets the device up (properties, library streams, the array's address);
+ * make that call outside any code that must not allocate.
+ * opts: device, hip_stream, words_per_thread, wg_size, tile_words and the word range as in
+ * fastlec_es_check; kernel must be AUTO or INTERP; deadline and cancel flag must be unset.
+ * Same answer fields as fastlec_es_check; kernel_ms is the host time from the first upload to
+ * the end of the wait (no HIP events are created).
+ * Errors: FASTLEC_ERR_INVALID when the bundled instruction stream does not fit the array
+ * (about 65,000 instructions), when the circuit's value file does not fit in LDS, or for the
+ * options above.  The array keeps the last call's contents; every call uploads all of it that
+ * it reads.  Calls on one device share the array: the library lets one run at a time per
+ * device (a host lock held until the call's results are on the host); calls that overlap on
+ * one device from outside this library's lock (another copy of the library in the process)
+ * would race. */
+int fastlec_es_check_noalloc(const fastlec_es_circuit *c, const fastlec_es_options *opts, fastlec_es_result *out);
+
 /* Release a handle (NULL is allowed). */
 void fastlec_es_free(fastlec_es_circuit *c);
 

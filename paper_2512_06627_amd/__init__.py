@@ -91,6 +91,8 @@ SIGNATURES = [
     ("fastlec_es_check", ctypes.c_int, [_P, ctypes.POINTER(fastlec_es_options), ctypes.POINTER(fastlec_es_result)]),
     ("fastlec_es_check_batch", ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_size_t, ctypes.POINTER(fastlec_es_options),
                                               ctypes.POINTER(fastlec_es_result)]),
+    ("fastlec_es_check_noalloc", ctypes.c_int, [_P, ctypes.POINTER(fastlec_es_options),
+                                                ctypes.POINTER(fastlec_es_result)]),
     ("fastlec_es_free", None, [_P]),
     ("fastlec_es_last_error", ctypes.c_char_p, []),
     ("fastlec_es_server_create", ctypes.c_int, [ctypes.POINTER(fastlec_es_options), ctypes.c_size_t, ctypes.POINTER(_P)]),
@@ -223,6 +225,17 @@ def fastlec_es_check(circuit: Circuit, **opts) -> dict:
     o = options(**opts)
     r = fastlec_es_result()
     rc = lib().fastlec_es_check(circuit.handle, ctypes.byref(o), ctypes.byref(r))
+    if rc:
+        _raise(rc, r.as_dict())
+    return r.as_dict()
+
+
+def fastlec_es_check_noalloc(circuit: Circuit, **opts) -> dict:
+    """fastlec_es_check on the interpreter, with the library's static device array instead of
+    device allocations; returns the result fields as a dict."""
+    o = options(**opts)
+    r = fastlec_es_result()
+    rc = lib().fastlec_es_check_noalloc(circuit.handle, ctypes.byref(o), ctypes.byref(r))
     if rc:
         _raise(rc, r.as_dict())
     return r.as_dict()

@@ -347,6 +347,28 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
     });
 }
 
+int fastlec_es_check_noalloc(const fastlec_es_circuit* c, const fastlec_es_options* opts, fastlec_es_result* out) {
+    return guarded([&] {
+        if (!c || !out) throw Error{kErrInvalid, "null argument"};
+        fastlec_es_options o = opts ? *opts : defaults();
+        if (o.kernel != FASTLEC_KERNEL_AUTO && o.kernel != FASTLEC_KERNEL_INTERP)
+            throw Error{kErrInvalid, "the no-allocation entry point runs only the interpreter with LDS value files"};
+        if (o.deadline_s > 0 || o.cancel_flag)
+            throw Error{kErrInvalid, "the no-allocation entry point takes no deadline or cancel flag"};
+        o.kernel = FASTLEC_KERNEL_INTERP;
+        Circuit& cc = const_cast<Circuit&>(c->c);
+        Device& dev = device(o.device);
+        hipStream_t stream = o.hip_stream ? (hipStream_t)o.hip_stream : dev.stream;
+        const HwRange r = range_of(cc.plan1.num_inputs, o.begin_word, o.end_word);
+        std::memset(out, 0, sizeof(*out));
+        double ms = 0;
+        const uint64_t best = noalloc_check(dev, cc, o, r, stream, &ms);
+        fill_result(cc, r, best, out);
+        out->kernel_ms = ms;
+        return FASTLEC_OK;
+    });
+}
+
 void fastlec_es_free(fastlec_es_circuit* c) { delete c; }
 
 // Compile the specialized kernel of a circuit without running it (no GPU needed).

@@ -186,6 +186,7 @@ Device& device(int ordinal) {
         throw Error{kErrDevice, std::string("built for gfx950, device is ") + d->prop.gcnArchName};
     FES_HIP(hipStreamCreateWithFlags(&d->stream, hipStreamNonBlocking));
     FES_HIP(hipStreamCreateWithFlags(&d->capture_stream, hipStreamNonBlocking));
+    noalloc_setup(*d);
     trace("device %d: %s, %d CUs, LDS %zu per block / %zu per CU", ordinal, d->prop.gcnArchName,
           d->prop.multiProcessorCount, (size_t)d->prop.sharedMemPerBlock, (size_t)d->prop.maxSharedMemoryPerMultiProcessor);
     Device& ref = *d;

@@ -116,8 +116,15 @@ struct Device {
     Buffer acquire(size_t bytes) { return acquire(bytes, bytes); }
     Buffer acquire(size_t dev_bytes, size_t host_bytes);
     void release(Buffer b);
+    // Device address of the no-allocation entry point's static scratch array on this device
+    // (looked up once, at set-up, with this device current).
+    void* noalloc_scratch = nullptr;
+    std::mutex noalloc_mu;  // one no-allocation check at a time per device
 };
 Device& device(int ordinal);
+
+// Set-up of the static scratch array for this device (its address on the device).
+void noalloc_setup(Device& dev);
 
 // Interpreter schedule: K half-words per lane, bundle B, workgroup size, tile size, tier.
 struct Schedule {
@@ -141,6 +148,11 @@ struct HwRange {
 };
 HwRange range_of(uint32_t n, uint64_t begin_word, uint64_t end_word);
 
+// Exact simulation of range r of circuit c on the interpreter with value files in LDS, using
+// only the device's static scratch array (no device or pinned allocation).  Returns the
+// lowest failing pattern (~0 when none); *ms = host time of launch and wait.
+uint64_t noalloc_check(Device& dev, Circuit& c, const fastlec_es_options& o, const HwRange& r, hipStream_t stream,
+                       double* ms);
 
 // Descriptors of an interpreter launch, written to `out` in longest-processing-time order
 // (most gate evaluations first); cone i reports into best[best_index[i]].  Returns the
