@@ -18,11 +18,11 @@ from .aig import Aig, import_into
 from .arith import (array_mult, wallace_mult, booth_wallace_mult,
                     mac_fused, mac_separate, ripple_add)
 from .miter import (miter_of, mult_pair, mult_miter, mac_miter, minterm_miter,
-                    inject_fault, layered_cone_miter, WORKLOADS, workload)
+                    inject_fault, layered_cone_miter, cone_batch, serve_pool, WORKLOADS, workload)
 
 __all__ = [
     "SplitMix64", "Aig", "import_into", "array_mult", "wallace_mult",
     "booth_wallace_mult", "mac_fused", "mac_separate", "ripple_add",
     "miter_of", "mult_pair", "mult_miter", "mac_miter", "minterm_miter",
-    "inject_fault", "layered_cone_miter", "WORKLOADS", "workload",
+    "inject_fault", "layered_cone_miter", "cone_batch", "serve_pool", "WORKLOADS", "workload",
 ]

@@ -233,6 +233,36 @@ def layered_cone_miter(seed: int, n: int, target_ands: int, fault_seed=None) -> 
     return miter_of(A, B)
 
 
+def cone_batch(seed: int, count: int, faulty: int, n_range, size_range):
+    """The batched-ES workload: ``count`` layered cone miters with n ~ U{n_range} inputs and
+    about U[size_range] AND gates, exactly ``faulty`` of them (a seeded choice) with an
+    injected fault.  Returns (miter, fault_seed or None) pairs; cone i uses generator seed
+    ``seed * 100000 + i``."""
+    rng = SplitMix64(seed)
+    bad = set()
+    while len(bad) < faulty:
+        bad.add(rng.below(count))
+    out = []
+    for i in range(count):
+        n, size = rng.between(*n_range), rng.between(*size_range)
+        fault = rng.between(1, 1 << 20) if i in bad else None
+        out.append((layered_cone_miter(seed * 100000 + i, n, size, fault_seed=fault), fault))
+    return out
+
+
+def serve_pool(rng: SplitMix64, seed: int, pool: int, n_range=(16, 34), size_range=(500, 20000)):
+    """The serving workload's pool: ``pool`` layered cone miters, n ~ U{n_range}, about
+    U[size_range] AND gates, each faulty with probability 1/10, drawn from ``rng`` (which the
+    caller goes on to use for the arrival stream).  Returns (miter, fault_seed or None) pairs;
+    cone i uses generator seed ``seed * 100000 + i``."""
+    out = []
+    for i in range(pool):
+        n, size = rng.between(*n_range), rng.between(*size_range)
+        fault = rng.between(1, 1 << 20) if rng.below(10) == 0 else None
+        out.append((layered_cone_miter(seed * 100000 + i, n, size, fault_seed=fault), fault))
+    return out
+
+
 # ---- named workloads -------------------------------------------------------
 
 def _mult_workload(w, impl, fault):

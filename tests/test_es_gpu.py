@@ -297,22 +297,6 @@ def test_specialized_lds_spills_match_oracle(monkeypatch):
         assert gpu_answer(c, kernel="specialized") == oracle.check(g.to_aag(), threads=8), i
 
 
-def test_wide_cones_specialized_vs_interpreter():
-    """Cones whose live values exceed the three-wave register budget run at two or one wave per
-    SIMD with LDS spills; their answers must equal the interpreter's (checked against the
-    oracle elsewhere) on the whole space."""
-    for size, n in ((12000, 22), (20000, 22)):
-        for fault in (None, 5):
-            g = miters.layered_cone_miter(900000 + size, n, size, fault_seed=fault)
-            c = es.fastlec_es_load_aig(g.to_aig())
-            src = es.fastlec_es_specialized_source(c, 3)
-            assert "one asm block:" in src and ("2 waves per SIMD" in src or "1 waves per SIMD" in src), size
-            if size == 20000:
-                assert "LDS spill" in src
-            print("wide cone", size, n, fault, flush=True)
-            assert gpu_answer(c, kernel="specialized") == gpu_answer(c, kernel="interp"), (size, fault)
-
-
 def test_per_gate_fallback_emitter_matches_oracle(monkeypatch):
     """The last-resort emitter (one asm statement per gate, compiler register allocation), used
     when a cone is too wide even for LDS spill slots, forced here on stored workloads."""
