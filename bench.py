@@ -22,13 +22,17 @@ sys.path.insert(0, ROOT)
 
 # Integer-VALU roofline of MI355X.  The published fp32 vector rate, 157.3 TFLOP/s = 256 CUs x
 # 2.4 GHz x 128 lanes x 2 flops per FMA, gives 128 32-bit lanes per CU per cycle, and a 32-bit
-# bitwise op issues at that lane rate (two wave64 VALU instructions per CU per cycle).  One
-# lane-op evaluates one AND gate on 32 patterns.
+# bitwise op issues at that lane rate (two wave64 VALU instructions per CU per cycle).  The
+# roofline's peak is the larger of that figure and the issue rate the library's probe measures
+# for the specialized kernel's instruction (fastlec_es_valu_probe: independent v_bitop3_b32
+# chains).  One lane-op of the algorithmic view evaluates one AND gate on 32 patterns.
 CUS, LANES_PER_CYCLE, CLOCK_HZ = 256, 128, 2.4e9
 PEAK_LANE_OPS = CUS * LANES_PER_CYCLE * CLOCK_HZ        # 7.86e13 int32 lane-ops/s
 PEAK_WAVE_INSTR = PEAK_LANE_OPS / 64                     # 1.23e12 wave64 VALU instructions/s
 PEAK_NODE_PATTERNS = PEAK_LANE_OPS * 32                   # 2.52e15 AND-node*patterns/s
 PEAK_HBM = 8.0e12                                        # bytes/s, MI355X HBM3E
+PROBE_WAVES = (1, 2, 3, 4, 6, 7)                         # waves per SIMD swept by the probe leg
+PROBE_ITERS = 20000                                      # 256 instructions per iteration
 
 
 # HBM bytes per launch of the 16x16 miter's specialized kernel, from rocprofv3 FETCH_SIZE and
@@ -47,24 +51,48 @@ def profiled_traffic(es, c):
     return None
 
 
-def executed_view(es, c, n, num_ands, kernel_s):
-    """Instructions the specialized kernel executes per 2,048-pattern pass (from its generated
-    body), and the VALU issue rate they imply."""
+def body_counts(es, c):
+    """(VALU, SALU) instructions of the specialized kernel's per-pass body (2,048 patterns per
+    wave pass), from its generated source; None when the kernel is not one asm block."""
     import re
-    src = es.fastlec_es_specialized_source(c, 2)
+    src = es.fastlec_es_specialized_source(c, 3)
     m = re.search(r"one asm block: (\d+) VGPRs, (\d+) SGPRs, (\d+) VALU and (\d+) SALU", src)
-    if not m:
-        return None
-    valu, salu = int(m.group(3)), int(m.group(4))
-    passes = 1 << max(0, n - 11)
-    rate = valu * passes / kernel_s
-    return {"valu_per_pass_body": valu, "salu_per_pass_body": salu, "passes": passes,
-            "valu_instr_per_s": rate, "valu_issue_peak": PEAK_WAVE_INSTR, "valu_issue_frac": rate / PEAK_WAVE_INSTR,
-            "and_gates_per_valu_instr": num_ands / valu}
+    return (int(m.group(3)), int(m.group(4))) if m else None
 
 
-def cpu_baseline(aag: bytes, num_ands: int, target_s: float = 12.0):
-    """The oracle (one pattern at a time, all host cores) on an ascending prefix of the space."""
+PROBE_VARIANTS = {0: "v_bitop3_b32, three VGPR sources in three banks", 1: "v_bitop3_b32, two VGPRs and an SGPR",
+                  2: "v_xor_b32, two VGPRs"}
+
+
+def valu_peak(es, waves=PROBE_WAVES, variants=(0, 1, 2), iters=PROBE_ITERS):
+    """The library's issue-rate probe for each operand form and occupancy; returns the rates and
+    the best (16 independent chains per wave, 256 instructions per loop iteration)."""
+    rows = []
+    for v in variants:
+        for w in waves:
+            es.fastlec_es_valu_probe(v, w, 100)  # first launch loads the code object
+            r = es.fastlec_es_valu_probe(v, w, iters)
+            rows.append({"variant": v, "waves_per_simd": w, "instr_per_s": r["instr_per_s"],
+                         "kernel_ms": r["kernel_ms"], "per_cu_per_clock_at_2_4_GHz": r["instr_per_s"] / CUS / CLOCK_HZ})
+    best = max(rows, key=lambda x: x["instr_per_s"])
+    return {"variants": {str(k): v for k, v in PROBE_VARIANTS.items() if k in variants}, "iters": iters,
+            "sweep": rows, "best_instr_per_s": best["instr_per_s"], "best_variant": best["variant"],
+            "best_waves_per_simd": best["waves_per_simd"], "spec_instr_per_s": PEAK_WAVE_INSTR}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(aag: bytes, num_ands: int, n: int, target_s: float = 12.0):
+    """The oracle (one pattern at a time, all host cores) on an ascending prefix of the space;
+    also its estimated time for the whole space at the measured rate."""
     import oracle
     c = oracle.Circuit(aag)
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
@@ -80,8 +108,11 @@ def cpu_baseline(aag: bytes, num_ands: int, target_s: float = 12.0):
             break
         patterns = min(1 << 30, int(patterns * max(2.0, min(16.0, target_s / max(dt, 1e-3)))))
         patterns = 1 << (patterns.bit_length() - 1)
-    return {"value": num_ands * ev / dt, "unit": "node*patterns/s", "cores": threads, "kind": "oracle",
-            "sample": f"patterns [0, {patterns}) of the same miter, {dt:.1f} s on {threads} threads"}
+    rate = num_ands * ev / dt
+    return {"value": rate, "unit": "node*patterns/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"patterns [0, {patterns}) of the same miter, {dt:.1f} s on {threads} threads",
+            "full_space_eta_s": num_ands * float(1 << n) / rate}
 
 
 def batch_leg(es, stream, seed: int = 4, count: int = 256, faulty: int = 26, n_range=(18, 30),
@@ -93,16 +124,10 @@ def batch_leg(es, stream, seed: int = 4, count: int = 256, faulty: int = 26, n_r
     specialized kernels, compiled together on the first call); one plain check per cone with the
     model's kernel choice once those kernels exist."""
     import miters
-    rng = miters.SplitMix64(seed)
-    bad = set()
-    while len(bad) < faulty:
-        bad.add(rng.below(count))
     t0 = time.perf_counter()
     cones, work = [], 0
-    for i in range(count):
-        n, size = rng.between(*n_range), rng.between(*size_range)
-        fault = rng.between(1, 1 << 20) if i in bad else None
-        c = es.fastlec_es_load_aig(miters.layered_cone_miter(seed * 100000 + i, n, size, fault_seed=fault).to_aig())
+    for g, _ in miters.cone_batch(seed, count, faulty, n_range, size_range):
+        c = es.fastlec_es_load_aig(g.to_aig())
         cones.append(c)
         info = c.info()
         work += info["num_ands_tfi"] * (1 << info["num_pis"])
@@ -136,6 +161,36 @@ def batch_leg(es, stream, seed: int = 4, count: int = 256, faulty: int = 26, n_r
             "plain_auto_cones_per_s": count / t_plain_auto, "batched_vs_plain_auto_speedup": t_plain_auto / t_batch,
             "identical_verdicts": plain == plain2 == interp_first == got_interp == first == got == plain_auto,
             "first_batch_call_s": t_first, "generate_s": gen_s}
+
+
+def interp_leg(es, stream, seed: int = 4, count: int = 256, faulty: int = 26, n_range=(18, 30),
+               size_range=(200, 5000), reps: int = 3):
+    """The interpreter alone on the batched workload's equivalent cones (every pattern simulated):
+    one plain check per cone, so each cone is its own launch.  Rate in stream instructions x
+    patterns per second (a fused three-AND XOR is one instruction) and in AND gates x patterns,
+    over the summed kernel times."""
+    import miters
+    cones = []
+    for g, fault in miters.cone_batch(seed, count, faulty, n_range, size_range):
+        if fault is None:
+            cones.append(es.fastlec_es_load_aig(g.to_aig()))
+    instr_work = and_work = 0
+    for c in cones:
+        i = c.info()
+        instr_work += (i["num_instrs"] - 2 * i["num_xors"]) * (1 << i["num_pis"])
+        and_work += i["num_ands_tfi"] * (1 << i["num_pis"])
+    for c in cones:  # uploads and schedules
+        es.fastlec_es_check(c, stream=stream, kernel="interp")
+    best = None
+    for _ in range(reps):
+        ms = 0.0
+        for c in cones:
+            r = es.fastlec_es_check(c, stream=stream, kernel="interp")
+            assert r["verdict"] == es.FASTLEC_EQUIVALENT
+            ms += r["kernel_ms"]
+        best = ms if best is None else min(best, ms)
+    return {"cones": len(cones), "kernel_ms_sum": best, "instr_patterns_per_s": instr_work / (best / 1e3),
+            "and_patterns_per_s": and_work / (best / 1e3)}
 
 
 def rsim_leg(es, stream, workload: str = "mult16_array_booth", words: int = 1 << 18, reps: int = 5):
@@ -233,10 +288,8 @@ def serve_leg(es, stream, seed: int = 5, seconds: float = 30.0, max_requests: in
     rng = miters.SplitMix64(seed)
     t0 = time.perf_counter()
     circs, gates = [], []
-    for i in range(pool):
-        n, size = rng.between(16, 34), rng.between(500, 20000)
-        fault = rng.between(1, 1 << 20) if rng.below(10) == 0 else None
-        c = es.fastlec_es_load_aig(miters.layered_cone_miter(seed * 100000 + i, n, size, fault_seed=fault).to_aig())
+    for g, _ in miters.serve_pool(rng, seed, pool):
+        c = es.fastlec_es_load_aig(g.to_aig())
         circs.append(c)
         gates.append(c.info()["num_ands_tfi"])
     gen_s = time.perf_counter() - t0
@@ -301,8 +354,9 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (HBM counter calibration)")
-    ap.add_argument("--leg", choices=["rsim", "sweep"], default=None,
-                    help="run only this secondary leg (random simulation or a sweeping pass) and print its JSON")
+    ap.add_argument("--leg", choices=["rsim", "sweep", "valu_peak", "interp", "batch"], default=None,
+                    help="run only this leg (random simulation, a sweeping pass or the VALU issue-rate "
+                         "probe) and print its JSON")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only: exact simulation here is a single-GPU build "
@@ -322,7 +376,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if a.leg:
-        leg = {"rsim": rsim_leg, "sweep": sweep_leg}[a.leg]
+        if a.leg == "valu_peak":
+            print(json.dumps({"leg": a.leg, **valu_peak(es)}), flush=True)
+            return
+        leg = {"rsim": rsim_leg, "sweep": sweep_leg, "interp": interp_leg, "batch": batch_leg}[a.leg]
         print(json.dumps({"leg": a.leg, **leg(es, stream)}), flush=True)
         return
     g = miters.workload(a.workload)
@@ -354,7 +411,30 @@ def main():
     ms_per_step = elapsed * 1e3 / a.steps
     value = node_patterns * a.steps / elapsed
     k_ms = sorted(kernel_ms)[len(kernel_ms) // 2]
-    achieved = node_patterns / (sum(kernel_ms) / len(kernel_ms) / 1e3)
+    k_mean_s = sum(kernel_ms) / len(kernel_ms) / 1e3
+    achieved_np = node_patterns / k_mean_s
+    # Roofline of the specialized kernel: executed wave64 VALU instructions per second (the
+    # generated body's count per 2,048-pattern pass times the passes of the space) against the
+    # issue peak, the larger of the published figure and the probe's measurement.
+    probe = valu_peak(es, waves=(3, 7), variants=(1, 2))
+    peak = max(PEAK_WAVE_INSTR, probe["best_instr_per_s"])
+    counts = body_counts(es, c) if a.kernel == "specialized" else None
+    passes = 1 << max(0, n - 11)
+    if counts:
+        valu, salu = counts
+        roofline = {"bound": "alu", "achieved": valu * passes / k_mean_s, "peak": peak, "unit": "wave64 VALU instr/s",
+                    "frac": valu * passes / k_mean_s / peak,
+                    "traffic": profiled_traffic(es, c),
+                    "kernel_ms_mean": k_mean_s * 1e3, "kernel_ms_median": k_ms,
+                    "valu_per_pass": valu, "salu_per_pass": salu, "passes": passes,
+                    "peak_spec": PEAK_WAVE_INSTR, "peak_probe": probe["best_instr_per_s"],
+                    "note": "achieved = VALU instructions of the generated per-pass body x 2^(n-11) passes / mean "
+                            "kernel time (HIP events); the loop adds about 6 VALU per pass (SQ_INSTS_VALU, profiles/); "
+                            "peak = max(256 CU x 2 wave64 instr/clk x 2.4 GHz, v_bitop3 probe)"}
+    else:
+        roofline = {"bound": "alu", "achieved": achieved_np, "peak": PEAK_NODE_PATTERNS, "unit": "node*patterns/s",
+                    "frac": achieved_np / PEAK_NODE_PATTERNS, "traffic": None, "kernel_ms_mean": k_mean_s * 1e3,
+                    "kernel_ms_median": k_ms, "note": "interpreter: algorithmic node*patterns against one lane-op per AND"}
     out = {
         "metric": "ES node*patterns/s (16x16 mult miter)",
         "value": value,
@@ -371,20 +451,18 @@ def main():
         "config": {"workload": f"{a.workload}: {n} inputs, 2^{n} patterns, {N} AND gates in cone, "
                                f"equivalent (all patterns simulated)",
                    "kernel": a.kernel, "peak_live_slots": info["peak_live_slots"]},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_NODE_PATTERNS,
-                     "unit": "node*patterns/s", "frac": achieved / PEAK_NODE_PATTERNS,
-                     "traffic": profiled_traffic(es, c) if a.kernel == "specialized" else None,
-                     "kernel_ms_median": k_ms,
-                     "note": "peak = 256 CU * 128 int32 lanes/cycle * 2.4 GHz * 32 patterns per lane-op "
-                             "(one lane-op per AND gate); achieved = N*2^n / mean kernel time (HIP events); "
-                             "a LUT instruction evaluates several AND gates, see executed"},
-        "executed": executed_view(es, c, n, N, sum(kernel_ms) / len(kernel_ms) / 1e3) if a.kernel == "specialized" else None,
+        "roofline": roofline,
+        "roofline_algorithmic": {"achieved": achieved_np, "one_op_per_and_peak": PEAK_NODE_PATTERNS,
+                                 "unit": "node*patterns/s", "ratio": achieved_np / PEAK_NODE_PATTERNS,
+                                 "and_gates_per_valu_instr": N / counts[0] if counts else None,
+                                 "note": "N*2^n per launch over a peak of one int32 lane-op per AND gate per 32 "
+                                         "patterns; above 1 because one LUT instruction evaluates several AND gates"},
         "load_ms": load_ms,
         "compile_ms": compile_ms,
         "all_steps_equivalent": bool(for_each_ok),
     }
     if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(g.to_aag(), N)
+        out["cpu_baseline"] = cpu_baseline(g.to_aag(), N, n)
     if not a.no_secondary:
         sec = {}
         mac = es.fastlec_es_load_aig(miters.workload("mac8_fused_separate").to_aig())

@@ -83,12 +83,20 @@ typedef struct {
     uint64_t end_word;
     double deadline_s;         /* > 0: stop with FASTLEC_TIMEOUT after this many seconds */
     volatile int *cancel_flag; /* host memory; nonzero = stop with FASTLEC_CANCELLED; may be NULL */
-    void *dev_scratch;         /* optional caller-owned device memory for control blocks (>= 4096 B) */
+    void *dev_scratch;         /* fastlec_es_check only, optional: caller-owned device memory on `device`
+                                  (256-byte aligned, dev_scratch_bytes long, e.g. a torch tensor) that
+                                  holds the launch's control block (claim counters, best value,
+                                  descriptor) and, on the device-memory interpreter tier, its value
+                                  files, instead of the library's buffers; written in the call's
+                                  stream order, free again when the call returns.  Too small or
+                                  misaligned: FASTLEC_ERR_INVALID naming the bytes needed.  Batches,
+                                  servers, simulation and fastlec_es_check_noalloc ignore it. */
     size_t dev_scratch_bytes;
 } fastlec_es_options;
 
 typedef struct {
-    int32_t verdict;             /* FASTLEC_EQUIVALENT / FASTLEC_NONEQUIVALENT, or a negative status in batch */
+    int32_t verdict;             /* FASTLEC_EQUIVALENT / FASTLEC_NONEQUIVALENT; a negative status on a
+                                    check stopped by its deadline or cancel flag, or a failed server job */
     uint32_t reserved;
     uint64_t cex;                /* lowest failing pattern in the range; valid iff NONEQUIVALENT */
     uint64_t patterns_evaluated; /* patterns whose miter value the answer establishes: the whole range when
@@ -99,6 +107,9 @@ typedef struct {
     double kernel_ms;            /* device time of the simulation kernel(s) */
     double queued_ms;            /* server: admission - submission (host steady clock); 0 otherwise */
     double latency_ms;           /* server: completion - submission (host steady clock); 0 otherwise */
+    double predicted_ms;         /* the runtime model's prediction (fastlec_es_predict): plain and batched
+                                    checks, the kernel time on the kernel that ran; server, the ETA at
+                                    admission = the job's interpreter time alone x the jobs in flight then */
 } fastlec_es_result;
 
 /* Fill *opts with defaults: device 0, library stream, tuned schedule, whole space. */
@@ -125,14 +136,16 @@ int fastlec_es_check(const fastlec_es_circuit *c, const fastlec_es_options *opts
  * option's word range is ignored).  With kernel AUTO, circuits that the runtime model
  * (fastlec_es_predict) gives to the specialized kernel are compiled together (up to 64 kernels
  * per hipRTC program) and run as their own launches (kernel_ms their own, compile_ms their
- * share of their program's compile).  Of the others, those predicted to take at least 1 ms on
- * the interpreter run as their own launches with their own schedule (unless the options fix
- * words_per_thread or wg_size); the rest are grouped by value-file size (powers of two of the
- * row count); each group is one persistent interpreter launch over all its cones, in
- * longest-processing-time order, with a tuned schedule (or the option's schedule fields) and
- * recorded once as a hipGraph; their kernel_ms is the sum over the groups.  cs: k handles;
- * out: k results.  Returns the first per-circuit error; per-circuit errors also appear as a
- * negative verdict. */
+ * share of their program's compile); a circuit whose kernel does not compile runs on the
+ * interpreter instead.  With kernel SPECIALIZED every circuit runs on its specialized kernel
+ * that way.  Of the others, those predicted to take at least 1 ms on the interpreter run as
+ * their own launches with their own schedule (unless the options fix words_per_thread or
+ * wg_size); the rest are grouped by value-file size (powers of two of the row count); each group
+ * is one persistent interpreter launch over all its cones, in longest-processing-time order by
+ * the runtime model's time, with a tuned schedule (or the option's schedule fields) and recorded
+ * once as a hipGraph; their kernel_ms is the sum over the groups.  cs: k handles; out: k
+ * results.  An error (a null handle, a device or runtime failure) fails the whole call with its
+ * status; the out entries are then not valid. */
 int fastlec_es_check_batch(const fastlec_es_circuit *const *cs, size_t k, const fastlec_es_options *opts,
                            fastlec_es_result *out);
 
@@ -187,7 +200,11 @@ typedef struct {
  * queue until admitted; a job is admitted when its charge fits beside the charges of the
  * jobs in flight: charge = peak_live_slots * min(W, chunk_words) * 8 bytes, the node-value
  * slots of its 64-pattern words in flight (W = 2^(n-6) words; chunk_words = 2^22 unless the
- * environment sets FASTLEC_ES_SERVER_CHUNK_WORDS).  Every step is one interpreter launch
+ * environment sets FASTLEC_ES_SERVER_CHUNK_WORDS).  The charge is a model of the memory a job
+ * would hold with its values materialised; the device memory the server really holds (its job
+ * table, about 2.3 MB, plus the value files of jobs too large for LDS, whose launch grid is
+ * capped to fit) is kept within budget_bytes too and reported as device_bytes.
+ * FASTLEC_ERR_INVALID if budget_bytes does not exceed the job table.  Every step is one interpreter launch
  * over the next slice of every job in flight, so jobs that arrive while others run share
  * the device with them; a job retires as soon as its answer is final (all patterns clean,
  * or the lowest failing pattern known).  Job descriptors and best-so-far values stay in a
@@ -299,6 +316,28 @@ int fastlec_es_submiter_aag(const fastlec_es_circuit *c, const uint32_t *class_o
  * choice of fastlec_es_check uses the same model. */
 int fastlec_es_predict(const fastlec_es_circuit *c, uint64_t begin_word, uint64_t end_word, double *interp_ms,
                        double *specialized_ms, double *compile_ms);
+
+/* ---- memory held by the library -------------------------------------------- */
+
+/* Bytes of device memory and of pinned host memory that the library's buffer pool holds on a
+ * device (in use or free for reuse), since the process started.  Per-circuit instruction
+ * streams, server tables, compiled kernels and the no-allocation array are not counted.
+ * Outputs may be NULL. */
+int fastlec_es_memory_get(int device, uint64_t *device_bytes, uint64_t *pinned_bytes);
+
+/* ---- roofline probe -------------------------------------------------------- */
+
+/* Issue rate of gfx950's integer VALU for the instructions the specialized kernel is made of:
+ * 16 independent chains (a result is read 16 instructions after it is written), 256
+ * instructions per loop iteration, waves_per_simd (1..8) waves per SIMD on every CU, iters
+ * (>= 1) iterations per wave.  variant 0: v_bitop3_b32 (a three-input LUT) with three VGPR
+ * sources in three different register banks; 1: v_bitop3_b32 with two VGPR sources and one
+ * SGPR; 2: v_xor_b32.  *instr_per_s = wave64 VALU instructions per second of the loop,
+ * *kernel_ms = kernel time (HIP events, the library's stream).  Outputs may be NULL.  This is
+ * the measured side of the specialized kernel's roofline (the published figure being 256 CUs x
+ * 128 lanes x 2.4 GHz, two wave64 instructions per CU per clock). */
+int fastlec_es_valu_probe(int device, uint32_t variant, uint32_t waves_per_simd, uint32_t iters,
+                          double *instr_per_s, double *kernel_ms);
 
 /* ---- diagnostics (no GPU needed) ------------------------------------------ */
 

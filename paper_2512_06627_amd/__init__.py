@@ -66,7 +66,7 @@ class fastlec_es_result(ctypes.Structure):
     _fields_ = [("verdict", ctypes.c_int32), ("reserved", ctypes.c_uint32), ("cex", ctypes.c_uint64),
                 ("patterns_evaluated", ctypes.c_uint64), ("next_word", ctypes.c_uint64),
                 ("plan_ms", ctypes.c_double), ("compile_ms", ctypes.c_double), ("kernel_ms", ctypes.c_double),
-                ("queued_ms", ctypes.c_double), ("latency_ms", ctypes.c_double)]
+                ("queued_ms", ctypes.c_double), ("latency_ms", ctypes.c_double), ("predicted_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
@@ -115,6 +115,10 @@ SIGNATURES = [
                                                  ctypes.POINTER(fastlec_es_options), ctypes.POINTER(ctypes.c_double)]),
     ("fastlec_es_classes", ctypes.c_int, [ctypes.POINTER(ctypes.c_uint64), ctypes.c_uint64,
                                           ctypes.POINTER(ctypes.c_uint32)]),
+    ("fastlec_es_memory_get", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_uint64),
+                                             ctypes.POINTER(ctypes.c_uint64)]),
+    ("fastlec_es_valu_probe", ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     ("fastlec_es_predict", ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     ("fastlec_es_submiter_aag", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint8),
@@ -132,6 +136,12 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise LibraryMissing(f"{LIB_PATH} not built: run paper_2512_06627_amd.build.build()")
+        # PyTorch ships its own HIP and HSA runtimes; loaded after this library has initialised
+        # the system ROCm runtime, it finds no GPU.  Loading it first lets both work in one process.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, res, args in SIGNATURES:
             f = getattr(L, name)
@@ -370,6 +380,25 @@ def fastlec_es_submiter_aag(circuit: Circuit, class_of, polarity, target: int):
     if rc:
         _raise(rc)
     return buf.value, list(ins[:k.value])
+
+
+def fastlec_es_memory_get(device: int = 0) -> dict:
+    """Device and pinned host bytes held by the library's buffer pool on a device."""
+    d, p = ctypes.c_uint64(), ctypes.c_uint64()
+    rc = lib().fastlec_es_memory_get(device, ctypes.byref(d), ctypes.byref(p))
+    if rc:
+        _raise(rc)
+    return {"device_bytes": d.value, "pinned_bytes": p.value}
+
+
+def fastlec_es_valu_probe(variant: int, waves_per_simd: int, iters: int, device: int = 0) -> dict:
+    """Issue rate of independent VALU chains (wave64 instructions/s) and kernel time; variant 0:
+    v_bitop3_b32 on three VGPRs, 1: on two VGPRs and an SGPR, 2: v_xor_b32."""
+    r, ms = ctypes.c_double(), ctypes.c_double()
+    rc = lib().fastlec_es_valu_probe(device, variant, waves_per_simd, iters, ctypes.byref(r), ctypes.byref(ms))
+    if rc:
+        _raise(rc)
+    return {"instr_per_s": r.value, "kernel_ms": ms.value}
 
 
 class Server:

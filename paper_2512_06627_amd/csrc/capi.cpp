@@ -122,13 +122,14 @@ void check_one(Circuit& c, const fastlec_es_options& o, fastlec_es_result* out) 
         }
         HwRange r{lo, std::min(full.end, lo + chunk)};
         double ms = 0;
+        const DevMem mem{o.dev_scratch, o.dev_scratch ? o.dev_scratch_bytes : 0};
         if (spec) {
-            run_jit(dev, c, *jk, r, o.tile_words ? 2ull * o.tile_words : 0, stream, nullptr, &best, &ms);
+            run_jit(dev, c, *jk, r, o.tile_words ? 2ull * o.tile_words : 0, stream, nullptr, &best, &ms, mem);
         } else {
             std::vector<Circuit*> one{&c};
             std::vector<HwRange> rs{r};
             std::vector<uint64_t> b;
-            run_interp(dev, one, rs, sch, stream, nullptr, b, &ms);
+            run_interp(dev, one, rs, sch, stream, nullptr, b, &ms, mem);
             best = b[0];
         }
         kernel_ms += ms;
@@ -146,6 +147,9 @@ void check_one(Circuit& c, const fastlec_es_options& o, fastlec_es_result* out) 
     fill_result(c, full, best, out);
     out->kernel_ms = kernel_ms;
     out->compile_ms = compile_ms;
+    const double patterns = 32.0 * (double)(full.end - full.begin);
+    out->predicted_ms = spec ? model_specialized_ms(c.lut_program().lut_steps, patterns)
+                             : model_interp_ms(c.interp_gates(), c.plan1.peak_slots, patterns);
 }
 
 }  // namespace
@@ -235,7 +239,12 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
         // taken when their summed saving also covers one program's fixed cost (same margin).
         std::vector<size_t> spec;
         std::vector<uint8_t> is_spec(k, 0);
-        if (o.kernel == FASTLEC_KERNEL_AUTO) {
+        if (o.kernel == FASTLEC_KERNEL_SPECIALIZED) {
+            for (size_t i = 0; i < k; ++i) {
+                is_spec[i] = 1;
+                spec.push_back(i);
+            }
+        } else if (o.kernel == FASTLEC_KERNEL_AUTO) {
             double saving = 0;
             for (size_t i = 0; i < k; ++i) {
                 Circuit& c = *v[i];
@@ -259,6 +268,38 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
                     else is_spec[i] = 0;
                 }
                 spec.swap(kept);
+            }
+        }
+        // Compile the routed cones' kernels together.  Under AUTO a cone whose kernel does not
+        // compile runs on the interpreter instead (the whole program is retried per cone first).
+        std::vector<std::shared_ptr<JitKernel>> jk;
+        std::vector<double> cms;
+        if (!spec.empty()) {
+            std::vector<Circuit*> sc;
+            for (size_t i : spec) sc.push_back(v[i]);
+            try {
+                jk = jit_kernels(sc, specialized_waves_per_eu(), &cms);
+            } catch (const Error& e) {
+                if (o.kernel == FASTLEC_KERNEL_SPECIALIZED) throw;
+                trace("batch: grouped compile failed (%s); compiling per cone", e.msg.c_str());
+                jk.assign(sc.size(), nullptr);
+                cms.assign(sc.size(), 0.0);
+                std::vector<size_t> kept;
+                std::vector<std::shared_ptr<JitKernel>> kept_k;
+                std::vector<double> kept_ms;
+                for (size_t j = 0; j < sc.size(); ++j) {
+                    try {
+                        double ms = 0;
+                        kept_k.push_back(jit_kernel(*sc[j], specialized_waves_per_eu(), &ms));
+                        kept_ms.push_back(ms);
+                        kept.push_back(spec[j]);
+                    } catch (const Error&) {
+                        is_spec[spec[j]] = 0;  // back to the interpreter
+                    }
+                }
+                spec.swap(kept);
+                jk.swap(kept_k);
+                cms.swap(kept_ms);
             }
         }
         // Interpreter cones predicted to take at least a millisecond gain nothing from sharing
@@ -311,6 +352,8 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
                 const size_t i = gi.second[t];
                 std::memset(&out[i], 0, sizeof(out[i]));
                 fill_result(*v[i], rs[i], best[t], &out[i]);
+                out[i].predicted_ms = model_interp_ms(v[i]->interp_gates(), v[i]->plan1.peak_slots,
+                                                      32.0 * (double)(rs[i].end - rs[i].begin));
             }
         }
         for (size_t i = 0; i < k; ++i)
@@ -326,12 +369,10 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
             std::memset(&out[i], 0, sizeof(out[i]));
             fill_result(*v[i], rs[i], best[0], &out[i]);
             out[i].kernel_ms = ms;
+            out[i].predicted_ms = model_interp_ms(v[i]->interp_gates(), v[i]->plan1.peak_slots,
+                                                  32.0 * (double)(rs[i].end - rs[i].begin));
         }
         if (!spec.empty()) {
-            std::vector<Circuit*> sc;
-            for (size_t i : spec) sc.push_back(v[i]);
-            std::vector<double> cms;
-            const std::vector<std::shared_ptr<JitKernel>> jk = jit_kernels(sc, specialized_waves_per_eu(), &cms);
             for (size_t j = 0; j < spec.size(); ++j) {
                 const size_t i = spec[j];
                 uint64_t best = ~0ull;
@@ -341,6 +382,8 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
                 fill_result(*v[i], rs[i], best, &out[i]);
                 out[i].kernel_ms = ms;
                 out[i].compile_ms = cms[j];
+                out[i].predicted_ms = model_specialized_ms(v[i]->lut_program().lut_steps,
+                                                           32.0 * (double)(rs[i].end - rs[i].begin));
             }
         }
         return FASTLEC_OK;
@@ -365,6 +408,7 @@ int fastlec_es_check_noalloc(const fastlec_es_circuit* c, const fastlec_es_optio
         const uint64_t best = noalloc_check(dev, cc, o, r, stream, &ms);
         fill_result(cc, r, best, out);
         out->kernel_ms = ms;
+        out->predicted_ms = model_interp_ms(cc.interp_gates(), cc.plan1.peak_slots, 32.0 * (double)(r.end - r.begin));
         return FASTLEC_OK;
     });
 }
@@ -526,6 +570,26 @@ int fastlec_es_predict(const fastlec_es_circuit* c, uint64_t begin_word, uint64_
             if (specialized_ms) *specialized_ms = model_specialized_ms(luts, patterns);
             if (compile_ms) *compile_ms = model_compile_ms(luts);
         }
+        return FASTLEC_OK;
+    });
+}
+
+int fastlec_es_memory_get(int dev_ordinal, uint64_t* device_bytes, uint64_t* pinned_bytes) {
+    return guarded([&] {
+        Device& dev = device(dev_ordinal);
+        std::lock_guard<std::mutex> g(dev.mu);
+        if (device_bytes) *device_bytes = dev.pool_device_bytes;
+        if (pinned_bytes) *pinned_bytes = dev.pool_pinned_bytes;
+        return FASTLEC_OK;
+    });
+}
+
+int fastlec_es_valu_probe(int dev_ordinal, uint32_t variant, uint32_t waves_per_simd, uint32_t iters,
+                          double* instr_per_s, double* kernel_ms) {
+    return guarded([&] {
+        Device& dev = device(dev_ordinal);
+        const double r = valu_probe(dev, variant, waves_per_simd, iters, dev.stream, kernel_ms);
+        if (instr_per_s) *instr_per_s = r;
         return FASTLEC_OK;
     });
 }

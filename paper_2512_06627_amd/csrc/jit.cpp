@@ -516,6 +516,14 @@ JitLaunchPlan jit_prepare(Device& dev, JitKernel& k, const HwRange& r, uint64_t 
             const int target = std::max(1, k.waves_used * 4 * 64 / k.block);
             k.per_device[dev.ordinal] = fn;
             k.blocks_per_cu[dev.ordinal] = std::max(1, std::min(b, target));
+            if (trace_on()) {
+                int regs = 0, spill = 0;
+                (void)hipFuncGetAttribute(&regs, HIP_FUNC_ATTRIBUTE_NUM_REGS, fn);
+                (void)hipFuncGetAttribute(&spill, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, fn);
+                trace("specialized kernel %s loaded: %d registers per lane, %d bytes of scratch, "
+                      "%d workgroups of %d per CU possible, %d used",
+                      k.name.c_str(), regs, spill, b, k.block, k.blocks_per_cu[dev.ordinal]);
+            }
         }
         lp.fn = k.per_device[dev.ordinal];
         blocks_per_cu = k.blocks_per_cu[dev.ordinal];
@@ -549,10 +557,11 @@ void jit_enqueue(const JitLaunchPlan& lp, uint64_t* next_item, uint64_t* best, c
 }
 
 void run_jit(Device& dev, Circuit& c, JitKernel& k, const HwRange& r, uint64_t tile_hw, hipStream_t stream,
-             const int* cancel, uint64_t* best_out, double* kernel_ms) {
+             const int* cancel, uint64_t* best_out, double* kernel_ms, DevMem mem) {
     (void)c;
     const JitLaunchPlan lp = jit_prepare(dev, k, r, tile_hw);
-    Buffer buf = dev.acquire(4096);
+    if (mem.ptr) check_dev_mem(mem, kClaimBytes + 8);
+    Buffer buf = dev.acquire(mem.ptr ? 0 : 4096, 4096);
     struct Releaser {
         Device& d;
         Buffer b;
@@ -563,7 +572,7 @@ void run_jit(Device& dev, Circuit& c, JitKernel& k, const HwRange& r, uint64_t t
     std::memset(host, 0, kClaimBytes);
     uint64_t* hbest = host + kClaimBytes / 8;
     *hbest = ~0ull;  // the claim counters at 0, best right after them
-    uint8_t* devp = (uint8_t*)buf.dev;
+    uint8_t* devp = (uint8_t*)(mem.ptr ? mem.ptr : buf.dev);
     uint64_t* next_item = (uint64_t*)devp;
     uint64_t* best = (uint64_t*)(devp + kClaimBytes);
     hipEvent_t e0, e1;

@@ -68,6 +68,11 @@ const Plan& Circuit::plan_for(uint32_t bundle) {
     return *it->second;
 }
 
+uint32_t Circuit::lut_steps_known() {
+    std::lock_guard<std::mutex> g(mu);
+    return lut ? lut->lut_steps : model_lut_steps_estimate(plan1.num_ands_tfi);
+}
+
 const LutProgram& Circuit::lut_program() {
     std::lock_guard<std::mutex> g(mu);
     if (!lut) lut = std::make_unique<LutProgram>(make_lut_program(aig, plan1, specialized_scalar_policy()));
@@ -149,7 +154,7 @@ Buffer Device::acquire(size_t dev_bytes, size_t host_bytes) {
     Buffer b;
     b.bytes = dev_bytes;
     b.host_bytes = host_bytes;
-    if (hipMalloc(&b.dev, dev_bytes) != hipSuccess) throw Error{kErrNoMem, "device allocation failed"};
+    if (dev_bytes && hipMalloc(&b.dev, dev_bytes) != hipSuccess) throw Error{kErrNoMem, "device allocation failed"};
     if (host_bytes && hipHostMalloc(&b.host, host_bytes, hipHostMallocDefault) != hipSuccess) {
         (void)hipFree(b.dev);
         throw Error{kErrNoMem, "pinned host allocation failed"};
@@ -308,13 +313,14 @@ uint64_t build_descs(Device& dev, const std::vector<Circuit*>& cs, const std::ve
                      const std::vector<uint32_t>& best_index, const Schedule& sch, hipStream_t stream,
                      ConeDesc* out) {
     const size_t k = cs.size();
-    // Longest-processing-time order: cones with the most gate evaluations get the lowest
-    // item numbers, so the big ones start first and the small ones fill the tail.
+    // Longest-processing-time order by the runtime model's interpreter time: the longest cones
+    // get the lowest item numbers, so they start first and the short ones fill the tail.
     std::vector<size_t> order(k);
     std::iota(order.begin(), order.end(), 0);
     std::vector<double> cost(k);
     for (size_t i = 0; i < k; ++i)
-        cost[i] = (double)cs[i]->plan_for(sch.B).prog.size() * (double)(ranges[i].end - ranges[i].begin);
+        cost[i] = lpt_cost_ms(cs[i]->interp_gates(), cs[i]->plan1.peak_slots,
+                              32.0 * (double)(ranges[i].end - ranges[i].begin));
     std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
     uint64_t item = 0;
     for (size_t t = 0; t < k; ++t) {
@@ -352,14 +358,24 @@ uint64_t fill_desc(const Plan& p, const Instr* prog, const HwRange& r, uint32_t 
     return d.item_end;
 }
 
+void check_dev_mem(const DevMem& m, size_t need) {
+    if ((uintptr_t)m.ptr % 256)
+        throw Error{kErrInvalid, "dev_scratch must be 256-byte aligned"};
+    if (m.bytes < need)
+        throw Error{kErrInvalid, "dev_scratch holds " + std::to_string(m.bytes) + " bytes; this check needs " +
+                                     std::to_string(need)};
+}
+
 void run_interp(Device& dev, const std::vector<Circuit*>& cs, const std::vector<HwRange>& ranges, const Schedule& sch,
-                hipStream_t stream, const int* cancel, std::vector<uint64_t>& best, double* kernel_ms) {
+                hipStream_t stream, const int* cancel, std::vector<uint64_t>& best, double* kernel_ms, DevMem mem) {
     const size_t k = cs.size();
     const uint32_t rows_max = rows_for(cs, sch.B);
     const size_t waves = (size_t)sch.grid * (sch.block / 64);
     const size_t file_bytes = sch.lds ? 0 : waves * rows_max * 64ull * sch.K * 4ull;
     Layout lay = layout(k, file_bytes);
-    Buffer buf = dev.acquire(lay.total, lay.files_off);
+    if (mem.ptr) check_dev_mem(mem, lay.total);
+    // With caller memory the pool only supplies the pinned staging of the control block.
+    Buffer buf = dev.acquire(mem.ptr ? 0 : lay.total, lay.files_off);
     struct Releaser {
         Device& d;
         Buffer b;
@@ -373,7 +389,7 @@ void run_interp(Device& dev, const std::vector<Circuit*>& cs, const std::vector<
     std::vector<uint32_t> idx(k);
     std::iota(idx.begin(), idx.end(), 0u);
     const uint64_t items = build_descs(dev, cs, ranges, idx, sch, stream, (ConeDesc*)(host + lay.desc_off));
-    uint8_t* devp = (uint8_t*)buf.dev;
+    uint8_t* devp = (uint8_t*)(mem.ptr ? mem.ptr : buf.dev);
     InterpLaunch L;
     L.cones = (const ConeDesc*)(devp + lay.desc_off);
     L.num_cones = (uint32_t)k;
@@ -412,32 +428,6 @@ void run_interp(Device& dev, const std::vector<Circuit*>& cs, const std::vector<
 }  // namespace fes
 
 namespace fes {
-
-// Fitted on one MI355X: median relative error 8% (interpreter), 16% (specialized), 1%
-// (compile); largest 28%, 61%, 4%.  Interpreter gates are the instructions of its bundled
-// stream (three-AND XORs count once).
-namespace model {
-constexpr double kInterpT0Ms = 0.0169;
-constexpr uint32_t kInterpSlotsBreak = 140;     // rate drops above: fewer waves per CU
-constexpr double kInterpRate = 4.62e13;         // gate instructions*patterns/s, value files of <= break slots
-constexpr double kInterpRateLarge = 2.71e13;    // above
-constexpr double kInterpMsPerGateFloor = 5.0e-5; // one wave pass per gate: spaces below a chip's waves
-constexpr double kSpecT0Ms = 0.0130;
-constexpr double kSpecLutPassesPerS = 6.33e11;
-constexpr double kCompileC0Ms = 104.1;
-constexpr double kCompileMsPerLut = 0.00649;
-}  // namespace model
-
-double model_interp_ms(uint32_t gates, uint32_t slots, double patterns) {
-    const double rate = slots > model::kInterpSlotsBreak ? model::kInterpRateLarge : model::kInterpRate;
-    return model::kInterpT0Ms + (double)gates * std::max(patterns / rate * 1e3, model::kInterpMsPerGateFloor);
-}
-
-double model_specialized_ms(uint32_t lut_steps, double patterns) {
-    return model::kSpecT0Ms + (double)lut_steps * std::max(1.0, patterns / 2048.0) / model::kSpecLutPassesPerS * 1e3;
-}
-
-double model_compile_ms(uint32_t lut_steps) { return model::kCompileC0Ms + model::kCompileMsPerLut * lut_steps; }
 
 void run_sim(Device& dev, Circuit& c, const uint32_t* pi, uint64_t words, uint32_t* sig,
              const fastlec_es_options* o, hipStream_t stream, double* kernel_ms) {

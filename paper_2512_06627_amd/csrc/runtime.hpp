@@ -12,6 +12,7 @@
 #include "../../include/fastlec_es.h"
 #include "aig.hpp"
 #include "kernels.hpp"
+#include "model.hpp"
 #include "plan.hpp"
 
 namespace fes {
@@ -87,6 +88,9 @@ struct Circuit {
     std::map<std::pair<int, uint32_t>, Instr*> dev_sim_prog;              // (device, bundle) -> stream
     ~Circuit();
     const LutProgram& lut_program();
+    // LUT steps of the specialized program if it is built, else the model's estimate (never
+    // builds it).
+    uint32_t lut_steps_known();
     const Plan& plan_for(uint32_t bundle);
     const Instr* device_prog(int device, uint32_t bundle, hipStream_t s);
     // Simulation covers every AND gate: the plan is made for the outputs plus every gate
@@ -167,10 +171,19 @@ uint64_t fill_desc(const Plan& p, const Instr* prog, const HwRange& r, uint32_t 
                    uint64_t item_begin, ConeDesc& d);
 uint32_t rows_for(const std::vector<Circuit*>& cs, int B);
 
+// Caller-owned device memory that replaces a launch's library buffer (fastlec_es_options
+// dev_scratch); null = the library's pool.
+struct DevMem {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+// Checks that caller memory of `m.bytes` can hold `need` bytes (alignment and size).
+void check_dev_mem(const DevMem& m, size_t need);
+
 // One interpreter launch over several cones (k = 1 for a plain check).
 void run_interp(Device& dev, const std::vector<Circuit*>& cs, const std::vector<HwRange>& ranges,
                 const Schedule& sch, hipStream_t stream, const int* cancel, std::vector<uint64_t>& best,
-                double* kernel_ms);
+                double* kernel_ms, DevMem mem = DevMem{});
 
 Schedule default_schedule(Device& dev, const std::vector<Circuit*>& cs, const fastlec_es_options* o);
 // The server's rule: bundles of B, the option's K (default 2) and workgroup (default 256),
@@ -181,20 +194,17 @@ Schedule shrink_schedule(Device& dev, const std::vector<Circuit*>& cs, const fas
 bool make_schedule(Device& dev, const std::vector<Circuit*>& cs, int K, int B, int block, bool lds, Schedule& out);
 bool make_schedule_rows(Device& dev, uint32_t rows, int K, int B, int block, bool lds, Schedule& out);
 
-// Runtime model of exact simulation on MI355X (the paper's form: linear in the gate count,
-// exponential in the input count, Section 3.2, runtime prediction), per kernel, with a fixed
-// launch cost; constants fitted by least squares on measured plain checks (32 cones, n 12..32).
-//  interpreter:  t = t0 + N * max(patterns / R, L), R by value-file size (S slots)
-//  specialized:  t = t0 + LUT steps * passes / R, passes = patterns / 2048 (at least 1)
-//  compile:      t = c0 + c1 * LUT steps
-double model_interp_ms(uint32_t gates, uint32_t slots, double patterns);
-double model_specialized_ms(uint32_t lut_steps, double patterns);
-double model_compile_ms(uint32_t lut_steps);
 
 // Sub-miter of candidate pair (target, class_of[target]) by virtual sweeping, as ASCII AIGER;
 // inputs (if not null) receives the original input index of each sub-miter input.
 std::string submiter_aag(const Aig& g, const uint32_t* class_of, const uint8_t* polarity, uint64_t rows,
                          uint32_t target, std::vector<uint32_t>* inputs);
+
+// Issue-rate probe (variant 0: v_bitop3_b32 on three VGPRs, 1: on two VGPRs and an SGPR,
+// 2: v_xor_b32), `waves_per_simd` waves per SIMD; returns wave64 VALU instructions per second
+// (kernel time in *ms).
+double valu_probe(Device& dev, uint32_t variant, uint32_t waves_per_simd, uint32_t iters, hipStream_t stream,
+                  double* ms);
 
 // Random-pattern simulation: value of every variable on `words` columns of input words
 // (pi: n rows, sig: max_var + 1 rows, both row-major on the device).
@@ -225,7 +235,7 @@ std::vector<std::shared_ptr<JitKernel>> jit_kernels(const std::vector<Circuit*>&
 // never waits: a kernel whose compile is in progress counts as not ready.
 std::shared_ptr<JitKernel> jit_ready(Circuit& c, int waves_per_eu);
 void run_jit(Device& dev, Circuit& c, JitKernel& k, const HwRange& r, uint64_t tile_hw, hipStream_t stream,
-             const int* cancel, uint64_t* best, double* kernel_ms);
+             const int* cancel, uint64_t* best, double* kernel_ms, DevMem mem = DevMem{});
 // The same launch in two parts, for callers that keep `best` and the claim counter in their
 // own device memory (the server): the grid and tiling of range r, then the launch alone.
 // *next_item must be zero when the kernel starts.

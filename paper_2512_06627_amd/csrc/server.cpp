@@ -189,19 +189,28 @@ void fastlec_es_server::plan_tiers(const std::vector<Job*>& act) {
     // its remaining work over its share of the interpreter's rate.
     size_t sharing = 0;
     for (Job* j : act) sharing += j->jit ? 0 : 1;
-    const double job_rate = rate / (double)std::max<size_t>(1, sharing);
     for (Job* j : act) {
         if (j->jit || j->compile_queued) continue;
         if (auto k = jit_ready(*j->c, specialized_waves_per_eu())) {
             j->jit = k;
             continue;
         }
-        // Remaining interpreter time at this job's share vs compile time (hipRTC: about 0.2 s
-        // plus 0.03 ms per AND gate for these kernels; compiles run one at a time).
-        const double gates = std::max<uint32_t>(1, j->c->plan1.num_gate_instrs);
-        const double interp_s = 32.0 * gates * (double)(j->range.end - j->cursor) / job_rate;
-        const double compile_s = 0.2 + 3e-5 * gates;
-        if (jit_mode == 2 || interp_s > 2.0 * compile_s + 0.5) {
+        // The runtime model's rule: remaining interpreter time at this job's share against the
+        // predicted compile time.  The LUT count is exact once the LUT program exists; it is
+        // only built here (host time) when the remaining time could pay for a compile at all.
+        TierJob tj;
+        tj.interp_gates = j->c->interp_gates();
+        tj.slots = j->c->plan1.peak_slots;
+        tj.remaining_patterns = 32.0 * (double)(j->range.end - j->cursor);
+        tj.lut_steps = 0;
+        double remaining_ms = 0;
+        server_wants_compile(tj, sharing, &remaining_ms, nullptr);
+        bool want = false;
+        if (remaining_ms > server_compile_threshold_ms()) {
+            tj.lut_steps = j->c->lut_steps_known();
+            want = server_wants_compile(tj, sharing, nullptr, nullptr);
+        }
+        if (jit_mode == 2 || want) {
             j->compile_queued = true;
             compile_queue.push_back(j);
             cv_compile.notify_one();
@@ -297,13 +306,28 @@ void fastlec_es_server::step(const std::vector<Job*>& act) {
             }
         }
         if (!have) g.sch = shrink_schedule(*dev, *g.c, &o, kB);
+        if (!g.sch.lds) {
+            // Value files in device memory: the grid is capped so that the server's device
+            // memory (job table plus files) stays within the budget.
+            const size_t per_block = (size_t)(g.sch.block / 64) * rows_for(*g.c, kB) * 64ull * g.sch.K * 4ull;
+            const size_t room = budget > table.bytes + 4096 ? budget - table.bytes - 4096 : 0;  // 4 KiB rounding
+            const size_t fit = room / per_block;
+            if (fit < 1)
+                throw Error{kErrNoMem, "the budget cannot hold one workgroup's value files in device memory"};
+            g.sch.grid = (int)std::min<size_t>((size_t)g.sch.grid, fit);
+        }
         g.items = build_descs(*dev, *g.c, *g.r, *g.i, g.sch, stream, (ConeDesc*)(host + g.desc_off));
         if (!g.sch.lds) {
             const size_t need = (size_t)g.sch.grid * (g.sch.block / 64) * rows_for(*g.c, kB) * 64ull * g.sch.K * 4ull;
-            if (files.bytes < need) {
-                if (files.dev) dev->release(files);
+            if (files.bytes < need) {  // device-only, exactly sized (not pooled), within the budget
+                if (files.dev) (void)hipFree(files.dev);
                 files = Buffer{};
-                files = dev->acquire(need, 0);  // device-only value files
+                const size_t bytes = (need + 4095) & ~size_t(4095);
+                if (hipMalloc(&files.dev, bytes) != hipSuccess) {
+                    files.dev = nullptr;
+                    throw Error{kErrNoMem, "device allocation of the server's value files failed"};
+                }
+                files.bytes = bytes;
             }
         }
     }
@@ -399,6 +423,11 @@ void fastlec_es_server::loop() {
                         j->slot = free_slots.back();
                         free_slots.pop_back();
                         j->t_admit = now;
+                        // The model's ETA: the job's interpreter time alone, times the jobs that
+                        // share the device with it at admission (itself included).
+                        j->res.predicted_ms = model_interp_ms(j->c->interp_gates(), j->c->plan1.peak_slots,
+                                                              32.0 * (double)(j->range.end - j->range.begin)) *
+                                              (double)(active.size() + 1);
                         st.charge_in_use_bytes += j->charge;
                         st.peak_charge_bytes = std::max(st.peak_charge_bytes, st.charge_in_use_bytes);
                         active.push_back(j);
@@ -479,6 +508,10 @@ int fastlec_es_server_create(const fastlec_es_options* opts, size_t budget_bytes
         s->off_desc_hbm = s->off_desc_lds + sizeof(ConeDesc) * kCapacity;
         s->off_ctl_jit = (s->off_desc_hbm + sizeof(ConeDesc) * kCapacity + 255) & ~size_t(255);
         s->table = s->dev->acquire(s->off_ctl_jit + kClaimBytes * kCapacity);
+        if (s->table.bytes >= budget_bytes) {
+            s->dev->release(s->table);
+            return FASTLEC_ERR_INVALID;  // the budget must exceed the job table
+        }
         for (uint32_t i = kCapacity; i-- > 0;) s->free_slots.push_back(i);
         s->st.budget_bytes = budget_bytes;
         fastlec_es_server* raw = s.get();
@@ -554,7 +587,7 @@ void fastlec_es_server_destroy(fastlec_es_server* s) {
     if (s->th.joinable()) s->th.join();
     if (s->compiler.joinable()) s->compiler.join();
     if (s->table.dev) s->dev->release(s->table);
-    if (s->files.dev) s->dev->release(s->files);
+    if (s->files.dev) (void)hipFree(s->files.dev);
     delete s;
 }
 

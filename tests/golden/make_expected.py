@@ -1,6 +1,6 @@
 """Write expected exact-simulation results of the named workloads, using only the oracle.
 
-    python tests/golden/make_expected.py [NAME ...]
+    python tests/golden/make_expected.py --resume PATH [NAME ...]
 
 Each workload is scanned in ascending windows of ``threads << window_log2``
 patterns; each window is one call of the oracle's multi-threaded scan, so the
@@ -67,8 +67,9 @@ if __name__ == "__main__":
     ap.add_argument("names", nargs="*")
     ap.add_argument("--threads", type=int, default=os.cpu_count())
     ap.add_argument("--window-log2", type=int, default=22)
-    ap.add_argument("--resume", default=os.path.join(HERE, "..", "..", "_work", "expected_resume.json"))
+    ap.add_argument("--resume", required=True,
+                    help="file that keeps the scan position after every window (any writable path)")
     a = ap.parse_args()
-    os.makedirs(os.path.dirname(a.resume), exist_ok=True)
+    os.makedirs(os.path.dirname(os.path.abspath(a.resume)), exist_ok=True)
     for name in a.names or DEFAULT:
         scan(name, a.threads, a.window_log2, a.resume, os.path.join(HERE, "expected.json"))

@@ -1,0 +1,82 @@
+"""The runtime model's decisions on the host (no GPU): the server's specialized-tier rule and
+the batch's longest-processing-time cost, on a fixed job set, against the model the library
+publishes through fastlec_es_predict.
+
+The server compiles a job's specialized kernel when its remaining interpreter time at its share
+of the device (the jobs on the interpreter share each step equally) exceeds the predicted
+specialized time of that work plus twice the predicted compile time.  The model driver (tests/sanitize/model_driver.cpp, built with
+AddressSanitizer and UBSan) calls the library's decision function directly.
+"""
+import os
+import re
+import subprocess
+
+import pytest
+
+import miters
+import paper_2512_06627_amd as es
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2512_06627_amd", "csrc")
+CLANG = "/opt/rocm/llvm/bin/clang++"
+
+
+@pytest.fixture(scope="module")
+def driver(tmp_path_factory):
+    if not os.path.exists(CLANG):
+        pytest.skip("clang++ not found")
+    out = str(tmp_path_factory.mktemp("model") / "model_driver")
+    cmd = [CLANG, "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+           "-I" + CSRC, os.path.join(ROOT, "tests", "sanitize", "model_driver.cpp"), os.path.join(CSRC, "model.cpp"),
+           "-o", out]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-3000:]
+    return out
+
+
+def _jobs():
+    out = [("mult6", miters.workload("mult6_array_wallace")), ("mult12", miters.workload("mult12_array_booth")),
+           ("mult16", miters.workload("mult16_array_booth")), ("mac8", miters.workload("mac8_fused_separate"))]
+    for i, (n, size) in enumerate(((18, 600), (24, 3000), (28, 5000), (34, 20000))):
+        out.append((f"layered{n}", miters.layered_cone_miter(700 + i, n, size)))
+    return out
+
+
+def _lut_steps(c):
+    return int(re.search(r"(\d+) LUT steps", es.fastlec_es_specialized_source(c, 3)).group(1))
+
+
+def test_server_tier_rule_follows_the_model(driver):
+    rows, expect = [], []
+    for name, g in _jobs():
+        c = es.fastlec_es_load_aig(g.to_aig())
+        i = c.info()
+        n = i["num_pis"]
+        gates = i["num_instrs"] - 2 * i["num_xors"]
+        luts = _lut_steps(c)
+        words = 1 << max(0, n - 6)
+        for left in (words, max(1, words // 16)):  # whole space left, a sixteenth left
+            p = es.fastlec_es_predict(c, words - left, words)
+            for sharing in (1, 8, 64):
+                rows.append(f"{gates} {i['peak_live_slots']} {luts} {32.0 * 2 * left if n >= 6 else 2.0 ** n} {sharing}")
+                expect.append((name, left, sharing, p))
+    r = subprocess.run([driver], input="\n".join(rows) + "\n", capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-3000:]
+    lines = r.stdout.split("\n")
+    wanted = {}
+    for line, (name, left, sharing, p) in zip(lines, expect):
+        want, rem, comp, alone, lpt, spec = line.split()
+        rem, comp, alone, lpt, spec = float(rem), float(comp), float(alone), float(lpt), float(spec)
+        assert alone == pytest.approx(p["interp_ms"], rel=1e-6), name
+        assert comp == pytest.approx(p["compile_ms"], rel=1e-6), name
+        assert spec == pytest.approx(p["specialized_ms"], rel=1e-6), name
+        assert rem == pytest.approx(sharing * p["interp_ms"], rel=1e-6), name
+        assert lpt == pytest.approx(p["interp_ms"], rel=1e-6), name  # LPT orders by the model's time
+        assert int(want) == (sharing * p["interp_ms"] > p["specialized_ms"] + 2.0 * p["compile_ms"]), (name, sharing)
+        wanted[(name, left, sharing)] = int(want)
+    # the fixed set spans both sides of the rule: the whole 16x16 space is worth a compile alone,
+    # the 6x6 miter never is, and a mid-size cone becomes worth one only when it shares the device
+    words16 = 1 << 26
+    assert wanted[("mult16", words16, 1)] == 1
+    assert all(wanted[("mult6", 64, s)] == 0 for s in (1, 8, 64))
+    assert wanted[("layered28", 1 << 22, 1)] == 0 and wanted[("layered28", 1 << 22, 64)] == 1

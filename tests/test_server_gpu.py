@@ -72,7 +72,10 @@ def test_server_budget_bounds_jobs_in_flight():
 def test_server_rejects_job_that_can_never_fit():
     g = miters.layered_cone_miter(5, 20, 800)
     c = es.fastlec_es_load_aig(g.to_aig())
-    srv = es.Server(1024)
+    i = c.info()
+    budget = 3 << 20  # above the server's job table (about 2.3 MB), below this job's charge
+    assert i["peak_live_slots"] * (1 << (i["num_pis"] - 6)) * 8 > budget
+    srv = es.Server(budget)
     with pytest.raises(es.EsError) as ei:
         srv.submit(c)
     assert ei.value.code == es.FASTLEC_REJECTED
