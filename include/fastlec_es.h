@@ -70,6 +70,8 @@ typedef struct {
     uint32_t levels;           /* logic depth of the cone */
     uint32_t num_xors;         /* three-AND XORs (x&y, ~x&~y, ~t1&~t2, inner gates read once) that the
                                   interpreter's bundled streams run as one XOR instruction each */
+    uint32_t interp_rows;      /* value-file rows of the interpreter's stream in bundles of 4 (constant,
+                                  inputs, slots, sink): up to 232 rows live in VGPRs (register tier) */
 } fastlec_es_info;
 
 typedef struct {
@@ -311,7 +313,7 @@ int fastlec_es_submiter_aag(const fastlec_es_circuit *c, const uint32_t *class_o
  *                   (num_instrs - 2 * num_xors); R depends on the value-file size (S)
  *   specialized_ms  t0 + (LUT steps) * max(1, patterns / 2048) / R
  *   compile_ms      hipRTC compile of the specialized kernel: c0 + c1 * (LUT steps)
- * Median errors on the fitting set: 8%, 16%, 1%.  Outputs may be NULL; asking for
+ * Median errors on the fitting set: 3%, 17%, 6%.  Outputs may be NULL; asking for
  * specialized_ms or compile_ms builds the circuit's LUT program (host time).  The AUTO kernel
  * choice of fastlec_es_check uses the same model. */
 int fastlec_es_predict(const fastlec_es_circuit *c, uint64_t begin_word, uint64_t end_word, double *interp_ms,

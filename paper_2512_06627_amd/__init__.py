@@ -50,7 +50,7 @@ class fastlec_es_info(ctypes.Structure):
     _fields_ = [("num_pis", ctypes.c_uint32), ("num_ands", ctypes.c_uint32),
                 ("num_ands_tfi", ctypes.c_uint32), ("num_outputs", ctypes.c_uint32),
                 ("peak_live_slots", ctypes.c_uint32), ("num_instrs", ctypes.c_uint32),
-                ("levels", ctypes.c_uint32), ("num_xors", ctypes.c_uint32)]
+                ("levels", ctypes.c_uint32), ("num_xors", ctypes.c_uint32), ("interp_rows", ctypes.c_uint32)]
 
 
 class fastlec_es_options(ctypes.Structure):

@@ -8,10 +8,11 @@ library's model (fastlec_es_predict) keeps that form per kernel and adds a
 fixed launch cost:
 
 * interpreter: t = t0 + N * max(2^n / R, L), N = gate instructions of its stream (AND gates
-  of the cone, each fused three-AND XOR counted once), with one rate R
-  for value files of at most ROWS_BREAK rows and another above (the workgroups a CU holds
-  halve there, and the interpreter is latency-bound); L is the time per gate of one wave's
-  pass, the floor when the space has fewer passes than the chip has waves;
+  of the cone, each fused three-AND XOR counted once), with one rate R per value-file tier
+  (register tier files of at most 96, 136 and 232 rows, at four, three and two waves per SIMD;
+  LDS or device memory above: the interpreter's rate follows the waves a SIMD holds); L is the
+  time per gate of one wave's pass, the floor when the space has fewer passes than the chip has
+  waves;
 * specialized kernel: t = t0 + L * passes / R, L = LUT steps of its program,
   passes = 2^(n-11) (2,048 patterns per wave pass);
 * hipRTC compile of the specialized kernel: t = c0 + c1 * L.
@@ -36,6 +37,8 @@ def cones():
             if target * (1 << n) > 3e12:
                 continue
             out.append((f"layered_n{n}_{target}", miters.layered_cone_miter(1000 + n * 7 + target, n, target)))
+    for n, target in ((16, 14000), (16, 20000), (18, 20000), (20, 16000), (22, 12000)):  # files above 232 rows
+        out.append((f"layered_n{n}_{target}", miters.layered_cone_miter(1000 + n * 7 + target, n, target)))
     for name in ("mult6_array_wallace", "mult12_array_booth", "mac8_fused_separate", "mult16_array_booth"):
         out.append((name, miters.workload(name)))
     return out
@@ -53,7 +56,7 @@ def measure(es, stream, reps=3):
         c = es.fastlec_es_load_aig(g.to_aig())
         info = c.info()
         rec = {"name": name, "n": info["num_pis"], "N": info["num_instrs"] - 2 * info["num_xors"],
-               "rows": info["peak_live_slots"],
+               "rows": info["interp_rows"],
                "luts": lut_steps(es, c)}
         if rec["N"] * (1 << rec["n"]) <= 3e12:
             es.fastlec_es_check(c, stream=stream, kernel="interp")
@@ -77,45 +80,57 @@ def fit_linear(x, t):
     return float(a), float(b), float(np.median(np.abs(rel))), float(np.max(np.abs(rel)))
 
 
-ROWS_BREAK = 140
+TIER_ROWS = (96, 136, 232)  # register tier files; LDS or device memory above
+
+
+def tier(rows):
+    for t, r in enumerate(TIER_ROWS):
+        if rows <= r:
+            return t
+    return len(TIER_ROWS)
 
 
 def fit_interp(ri):
-    """t ~ t0 + N max(2^n / R, L), R = R_lo or R_hi by rows; L by a search over a grid, the
-    rest by least squares on relative error."""
+    """t ~ t0 + N max(2^n / R_tier, L): L by a search over a grid, t0 and the tier rates by least
+    squares on relative error (a tier without data keeps no rate)."""
     t = np.array([r["interp_ms"] for r in ri])
     N = np.array([float(r["N"]) for r in ri])
     P = np.array([2.0 ** r["n"] for r in ri])
-    hi = np.array([r["rows"] > ROWS_BREAK for r in ri])
+    tr = np.array([tier(r["rows"]) for r in ri])
+    tiers = sorted(set(tr.tolist()))
     best = None
     for L in np.geomspace(1e-6, 1e-3, 61):  # ms per gate
-        # for fixed L the model is linear in (t0, 1/R_lo, 1/R_hi) where N P / R exceeds N L;
-        # iterate the split twice from "rate everywhere"
+        # for fixed L the model is linear in (t0, 1/R_tier) where N P / R exceeds N L; iterate
+        # the split from "rate everywhere"
         use_rate = np.ones_like(t, dtype=bool)
         for _ in range(3):
-            A = np.stack([np.ones_like(t), np.where(use_rate & ~hi, N * P, 0), np.where(use_rate & hi, N * P, 0)], axis=1)
+            cols = [np.ones_like(t)] + [np.where(use_rate & (tr == k), N * P, 0) for k in tiers]
+            A = np.stack(cols, axis=1)
             y = t - np.where(use_rate, 0, N * L)
-            (a, b_lo, b_hi), *_ = np.linalg.lstsq(A / t[:, None], y / t, rcond=None)
-            b = np.where(hi, b_hi, b_lo)
+            coef, *_ = np.linalg.lstsq(A / t[:, None], y / t, rcond=None)
+            a = coef[0]
+            b = np.zeros_like(t)
+            for j, k in enumerate(tiers):
+                b[tr == k] = coef[1 + j]
             use_rate = P * b > L
         pred = a + N * np.maximum(P * b, L)
         rel = pred / t - 1
         score = np.median(np.abs(rel)) + 0.25 * np.max(np.abs(rel))
         if best is None or score < best[0]:
-            best = (score, float(a), float(b_lo), float(b_hi), float(L),
-                    float(np.median(np.abs(rel))), float(np.max(np.abs(rel))))
+            rates = {int(k): float(1e3 / coef[1 + j]) for j, k in enumerate(tiers)}
+            best = (score, float(a), rates, float(L), float(np.median(np.abs(rel))), float(np.max(np.abs(rel))))
     return best[1:]
 
 
 def fit(rows):
     ri = [r for r in rows if "interp_ms" in r]
-    a_i, b_lo, b_hi, L_i, med_i, max_i = fit_interp(ri)
+    a_i, rates, L_i, med_i, max_i = fit_interp(ri)
     a_s, b_s, med_s, max_s = fit_linear([r["luts"] * 2.0 ** max(0, r["n"] - 11) for r in rows],
                                         [r["specialized_ms"] for r in rows])
     rc = [r for r in rows if r["compile_ms"] > 0]
     a_c, b_c, med_c, max_c = fit_linear([r["luts"] for r in rc], [r["compile_ms"] for r in rc])
-    return {"interp_t0_ms": a_i, "interp_rows_break": ROWS_BREAK,
-            "interp_node_patterns_per_s": 1e3 / b_lo, "interp_node_patterns_per_s_above_break": 1e3 / b_hi,
+    return {"interp_t0_ms": a_i, "interp_tier_rows": list(TIER_ROWS),
+            "interp_gate_patterns_per_s_by_tier": rates,
             "interp_ms_per_gate_floor": L_i,
             "interp_median_rel_err": med_i, "interp_max_rel_err": max_i,
             "specialized_t0_ms": a_s, "specialized_lut_passes_per_s": 1e3 / b_s,

@@ -50,7 +50,9 @@ Schedule autotune(Device& dev, const std::vector<Circuit*>& cs, const std::vecto
         auto it = tune_cache().find(key);
         if (it != tune_cache().end()) {
             Schedule s;
-            if (make_schedule(dev, cs, it->second.K, it->second.B, it->second.block, it->second.lds, s)) return s;
+            if (it->second.regs ? make_schedule_regs(dev, rows_for(cs, 4), s)
+                                : make_schedule(dev, cs, it->second.K, it->second.B, it->second.block, it->second.lds, s))
+                return s;
             trace("autotune: cached K=%d B=%d block=%d does not fit this batch; re-tuning", it->second.K,
                   it->second.B, it->second.block);
         }
@@ -67,6 +69,10 @@ Schedule autotune(Device& dev, const std::vector<Circuit*>& cs, const std::vecto
         sample_work += per_hw * (double)hw;
     }
     std::vector<Schedule> cands;
+    {
+        Schedule rs;
+        if (!hbm && make_schedule_regs(dev, rows_for(cs, 4), rs)) cands.push_back(rs);
+    }
     for (int K : {1, 2, 4})
         for (int B : {4, 8, 16})
             for (int block : {64, 128, 256}) {
@@ -99,7 +105,8 @@ Schedule autotune(Device& dev, const std::vector<Circuit*>& cs, const std::vecto
     for (const Schedule& s : cands) {
         run_interp(dev, cs, sample, s, stream, nullptr, b, &ms);
         const double rate = sample_work / std::max(1e-3, (double)ms);
-        trace("autotune: K=%d B=%d block=%d grid=%d %s -> %.3f ms", s.K, s.B, s.block, s.grid, s.lds ? "lds" : "hbm", ms);
+        trace("autotune: K=%d B=%d block=%d grid=%d %s -> %.3f ms", s.K, s.B, s.block, s.grid,
+              s.regs ? "regs" : s.lds ? "lds" : "hbm", ms);
         if (rate > best_rate) {
             best_rate = rate;
             best = s;
@@ -147,7 +154,7 @@ void run_batch_graph(Device& dev, const std::vector<Circuit*>& cs, const std::ve
     BatchGraph* bg = nullptr;
     for (auto& x : list)
         if (x->uids == uids && x->sch.K == sch.K && x->sch.B == sch.B && x->sch.block == sch.block &&
-            x->sch.grid == sch.grid && x->sch.lds == sch.lds && x->sch.tile_hw == sch.tile_hw)
+            x->sch.grid == sch.grid && x->sch.lds == sch.lds && x->sch.tile_hw == sch.tile_hw && x->sch.regs == sch.regs)
             bg = x.get();
     if (!bg) {
         if (list.size() >= 16) {  // evict the least recently used graph (a batch may hold several groups)
@@ -167,7 +174,7 @@ void run_batch_graph(Device& dev, const std::vector<Circuit*>& cs, const std::ve
         const size_t waves = (size_t)sch.grid * (sch.block / 64);
         const size_t desc_off = (sizeof(LaunchCtl) + 8 * k + 63) & ~size_t(63);
         const size_t files_off = (desc_off + sizeof(ConeDesc) * k + 255) & ~size_t(255);
-        const size_t file_bytes = sch.lds ? 0 : waves * rows_max * 64ull * sch.K * 4ull;
+        const size_t file_bytes = (sch.lds || sch.regs) ? 0 : waves * rows_max * 64ull * sch.K * 4ull;
         nb->best_off = sizeof(LaunchCtl);
         nb->total = files_off + file_bytes;
         nb->buf = dev.acquire(nb->total, files_off);
@@ -185,7 +192,7 @@ void run_batch_graph(Device& dev, const std::vector<Circuit*>& cs, const std::ve
         L.total_items = items;
         L.ctl = (LaunchCtl*)devp;
         L.best = (unsigned long long*)(devp + nb->best_off);
-        L.hbm_rows = sch.lds ? nullptr : (uint32_t*)(devp + files_off);
+        L.hbm_rows = (sch.lds || sch.regs) ? nullptr : (uint32_t*)(devp + files_off);
         L.cancel = nullptr;
         // Recorded on a stream used for nothing else (a null caller stream cannot be
         // captured); the graph is launched on the caller's stream.  The host staging area
@@ -194,7 +201,7 @@ void run_batch_graph(Device& dev, const std::vector<Circuit*>& cs, const std::ve
         (void)hipGetLastError();
         hipError_t e = hipStreamBeginCapture(dev.capture_stream, hipStreamCaptureModeRelaxed);
         if (e == hipSuccess) e = hipMemcpyAsync(devp, host, files_off, hipMemcpyHostToDevice, dev.capture_stream);
-        if (e == hipSuccess) e = launch_interp(L, sch.K, sch.B, sch.lds, sch.grid, sch.block, dev.capture_stream);
+        if (e == hipSuccess) e = launch_schedule(L, sch, dev.capture_stream);
         hipGraph_t graph = nullptr;
         hipError_t e_end = hipStreamEndCapture(dev.capture_stream, &graph);
         if (e == hipSuccess) e = e_end;

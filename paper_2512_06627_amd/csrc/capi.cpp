@@ -80,7 +80,7 @@ bool use_specialized(Circuit& c, const fastlec_es_options& o, const HwRange& r) 
     if (o.kernel == FASTLEC_KERNEL_SPECIALIZED) return true;
     if (o.kernel != FASTLEC_KERNEL_AUTO) return false;
     const double patterns = 32.0 * (double)(r.end - r.begin);
-    const double t_interp = model_interp_ms(c.interp_gates(), c.plan1.peak_slots, patterns);
+    const double t_interp = model_interp_ms(c.interp_gates(), c.interp_rows(), patterns);
     if (jit_ready(c, specialized_waves_per_eu()))
         return model_specialized_ms(c.lut_program().lut_steps, patterns) < t_interp;
     if (t_interp < kCompileMargin * model_compile_ms(0)) return false;
@@ -149,7 +149,7 @@ void check_one(Circuit& c, const fastlec_es_options& o, fastlec_es_result* out) 
     out->compile_ms = compile_ms;
     const double patterns = 32.0 * (double)(full.end - full.begin);
     out->predicted_ms = spec ? model_specialized_ms(c.lut_program().lut_steps, patterns)
-                             : model_interp_ms(c.interp_gates(), c.plan1.peak_slots, patterns);
+                             : model_interp_ms(c.interp_gates(), c.interp_rows(), patterns);
 }
 
 }  // namespace
@@ -204,6 +204,7 @@ int fastlec_es_info_get(const fastlec_es_circuit* c, fastlec_es_info* info) {
         info->num_instrs = p.num_gate_instrs;
         info->levels = p.levels;
         info->num_xors = c->c.fused_xors;
+        info->interp_rows = const_cast<Circuit&>(c->c).plan_for(4).rows;
         return FASTLEC_OK;
     });
 }
@@ -249,7 +250,7 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
             for (size_t i = 0; i < k; ++i) {
                 Circuit& c = *v[i];
                 const double patterns = 32.0 * (double)(rs[i].end - rs[i].begin);
-                const double ti = model_interp_ms(c.interp_gates(), c.plan1.peak_slots, patterns);
+                const double ti = model_interp_ms(c.interp_gates(), c.interp_rows(), patterns);
                 if (ti < kCompileMargin * (model_compile_ms(0) / 64.0)) continue;  // cheap cone: no LUT program
                 const uint32_t luts = c.lut_program().lut_steps;
                 const double ts = model_specialized_ms(luts, patterns);
@@ -312,7 +313,7 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
                 if (is_spec[i]) continue;
                 Circuit& c = *v[i];
                 const double patterns = 32.0 * (double)(rs[i].end - rs[i].begin);
-                if (model_interp_ms(c.interp_gates(), c.plan1.peak_slots, patterns) >= 1.0) {
+                if (model_interp_ms(c.interp_gates(), c.interp_rows(), patterns) >= 1.0) {
                     is_alone[i] = 1;
                     alone.push_back(i);
                 }
@@ -352,7 +353,7 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
                 const size_t i = gi.second[t];
                 std::memset(&out[i], 0, sizeof(out[i]));
                 fill_result(*v[i], rs[i], best[t], &out[i]);
-                out[i].predicted_ms = model_interp_ms(v[i]->interp_gates(), v[i]->plan1.peak_slots,
+                out[i].predicted_ms = model_interp_ms(v[i]->interp_gates(), v[i]->interp_rows(),
                                                       32.0 * (double)(rs[i].end - rs[i].begin));
             }
         }
@@ -369,7 +370,7 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
             std::memset(&out[i], 0, sizeof(out[i]));
             fill_result(*v[i], rs[i], best[0], &out[i]);
             out[i].kernel_ms = ms;
-            out[i].predicted_ms = model_interp_ms(v[i]->interp_gates(), v[i]->plan1.peak_slots,
+            out[i].predicted_ms = model_interp_ms(v[i]->interp_gates(), v[i]->interp_rows(),
                                                   32.0 * (double)(rs[i].end - rs[i].begin));
         }
         if (!spec.empty()) {
@@ -408,7 +409,7 @@ int fastlec_es_check_noalloc(const fastlec_es_circuit* c, const fastlec_es_optio
         const uint64_t best = noalloc_check(dev, cc, o, r, stream, &ms);
         fill_result(cc, r, best, out);
         out->kernel_ms = ms;
-        out->predicted_ms = model_interp_ms(cc.interp_gates(), cc.plan1.peak_slots, 32.0 * (double)(r.end - r.begin));
+        out->predicted_ms = model_interp_ms(cc.interp_gates(), cc.interp_rows(), 32.0 * (double)(r.end - r.begin));
         return FASTLEC_OK;
     });
 }
@@ -564,7 +565,7 @@ int fastlec_es_predict(const fastlec_es_circuit* c, uint64_t begin_word, uint64_
         const HwRange r = range_of(cc.plan1.num_inputs, begin_word, end_word);
         const double patterns = 32.0 * (double)(r.end - r.begin);
         if (interp_ms)
-            *interp_ms = model_interp_ms(cc.interp_gates(), cc.plan1.peak_slots, patterns);
+            *interp_ms = model_interp_ms(cc.interp_gates(), cc.interp_rows(), patterns);
         if (specialized_ms || compile_ms) {
             const uint32_t luts = cc.lut_program().lut_steps;
             if (specialized_ms) *specialized_ms = model_specialized_ms(luts, patterns);

@@ -253,7 +253,257 @@ hipError_t launch_k(const InterpLaunch& L, int B, bool lds, int grid, int block,
     }
 }
 
+// ---- register tier ------------------------------------------------------------------------
+//
+// The value file of a wave in its own VGPRs instead of LDS.  With files in LDS a CU holds about
+// 160 KB / (rows x 256 B) waves, about one per SIMD for the usual cones, and one wave issues at
+// most one instruction every few cycles, so the interpreter runs at the issue rate of a single
+// wave per SIMD.  The VGPR file is 512 KB per CU: the same cones fit two to four waves per SIMD.
+//
+// Row r of the file is v[kFileBase + r]; rows are read and written through gfx950's GPR index
+// mode (s_set_gpr_idx_on / _idx / _off: the low 8 bits of an SGPR offset the register number of
+// the indexed operand), so the file needs no address arithmetic.  The index is taken from the
+// instruction words themselves: only their low 8 bits count, so a row with its complement flag
+// in bit 31 indexes the right register.  Bundles of four gates keep the stream's
+// read-all-then-write-all semantics: the eight operands go to v16..v23, the four results are
+// computed and written back.  The instruction stream comes in by scalar loads, one bundle
+// (64 bytes) ahead into a second set of SGPRs; with no LDS operations in the pass, the scalar
+// wait counter tracks only those loads.
+//
+// One pass (2,048 patterns: 64 lanes x 32) is one asm statement.  It owns v16..v(kFileBase+R-1),
+// s62..s99 and m0.  Inputs: the stream, the bundle count, n, the pass's first half-word index
+// (bits 6 and up give inputs 11 and up) and the lane words of inputs 5..10.  Output: the lane's
+// miter word.
+constexpr int kFileBase = 24;
+
+#define FES_RG_READS(X0, X1, X4, X5, X8, X9, X12, X13)           \
+    "s_set_gpr_idx_on " X0 ", gpr_idx(SRC0)\n"                   \
+    "v_mov_b32 v16, v24\n"                                        \
+    "s_set_gpr_idx_idx " X1 "\n"                                  \
+    "v_mov_b32 v17, v24\n"                                        \
+    "s_set_gpr_idx_idx " X4 "\n"                                  \
+    "v_mov_b32 v18, v24\n"                                        \
+    "s_set_gpr_idx_idx " X5 "\n"                                  \
+    "v_mov_b32 v19, v24\n"                                        \
+    "s_set_gpr_idx_idx " X8 "\n"                                  \
+    "v_mov_b32 v20, v24\n"                                        \
+    "s_set_gpr_idx_idx " X9 "\n"                                  \
+    "v_mov_b32 v21, v24\n"                                        \
+    "s_set_gpr_idx_idx " X12 "\n"                                 \
+    "v_mov_b32 v22, v24\n"                                        \
+    "s_set_gpr_idx_idx " X13 "\n"                                 \
+    "v_mov_b32 v23, v24\n"                                        \
+    "s_set_gpr_idx_off\n"
+// gate u: operands in TA/TB, instruction words A (a), B (b), F (flags); result left in TA
+#define FES_RG_GATE(TA, TB, A, B, F, LBL)                        \
+    "s_ashr_i32 s96, " A ", 31\n"                                 \
+    "v_xor_b32 " TA ", s96, " TA "\n"                             \
+    "s_ashr_i32 s96, " B ", 31\n"                                 \
+    "v_xor_b32 " TB ", s96, " TB "\n"                             \
+    "s_bfe_i32 s96, " F ", 0x10002\n"                             \
+    "v_bitop3_b32 " TA ", " TA ", " TB ", s96 bitop3:0x68\n"      \
+    "s_and_b32 s97, " F ", 3\n"                                   \
+    "s_cbranch_scc0 " LBL "_%=\n"                                 \
+    "s_bfe_i32 s96, " F ", 0x10000\n"                             \
+    "s_bfe_i32 s97, " F ", 0x10001\n"                             \
+    "v_mov_b32 " TB ", s97\n"                                     \
+    "v_bitop3_b32 " TB ", " TA ", s96, " TB " bitop3:0xca\n"      \
+    "v_or_b32 %[m], %[m], " TB "\n"                               \
+    LBL "_%=:\n"
+#define FES_RG_WRITES(X2, X6, X10, X14)                          \
+    "s_set_gpr_idx_on " X2 ", gpr_idx(DST)\n"                    \
+    "v_mov_b32 v24, v16\n"                                        \
+    "s_set_gpr_idx_idx " X6 "\n"                                  \
+    "v_mov_b32 v24, v18\n"                                        \
+    "s_set_gpr_idx_idx " X10 "\n"                                 \
+    "v_mov_b32 v24, v20\n"                                        \
+    "s_set_gpr_idx_idx " X14 "\n"                                 \
+    "v_mov_b32 v24, v22\n"                                        \
+    "s_set_gpr_idx_off\n"
+#define FES_RG_BUFFER(b0, b1, b2, b3, b4, b5, b6, b7, b8, b9, b10, b11, b12, b13, b14, b15, P)             \
+    FES_RG_READS(b0, b1, b4, b5, b8, b9, b12, b13)                                                         \
+    FES_RG_GATE("v16", "v17", b0, b1, b3, "fes_rg" P "_g0")                                                \
+    FES_RG_GATE("v18", "v19", b4, b5, b7, "fes_rg" P "_g1")                                                \
+    FES_RG_GATE("v20", "v21", b8, b9, b11, "fes_rg" P "_g2")                                               \
+    FES_RG_GATE("v22", "v23", b12, b13, b15, "fes_rg" P "_g3")                                             \
+    FES_RG_WRITES(b2, b6, b10, b14)
+#define FES_RG_BUF_A                                                                                      \
+    FES_RG_BUFFER("s64", "s65", "s66", "s67", "s68", "s69", "s70", "s71", "s72", "s73", "s74", "s75", "s76", \
+                  "s77", "s78", "s79", "a")
+#define FES_RG_BUF_B                                                                                      \
+    FES_RG_BUFFER("s80", "s81", "s82", "s83", "s84", "s85", "s86", "s87", "s88", "s89", "s90", "s91", "s92", \
+                  "s93", "s94", "s95", "b")
+
+#define FES_RG_INPUT(I, ROW, VAL)            \
+    "s_cmp_eq_u32 %[n], " #I "\n"            \
+    "s_cbranch_scc1 fes_rg_in_done_%=\n"     \
+    "v_mov_b32 " ROW ", " VAL "\n"
+
+#define FES_RG_PASS_ASM                                                                                   \
+    "v_mov_b32 v24, 0\n"                                                                                  \
+    FES_RG_INPUT(0, "v25", "0xaaaaaaaa") FES_RG_INPUT(1, "v26", "0xcccccccc")                              \
+    FES_RG_INPUT(2, "v27", "0xf0f0f0f0") FES_RG_INPUT(3, "v28", "0xff00ff00")                              \
+    FES_RG_INPUT(4, "v29", "0xffff0000") FES_RG_INPUT(5, "v30", "%[x5]") FES_RG_INPUT(6, "v31", "%[x6]")    \
+    FES_RG_INPUT(7, "v32", "%[x7]") FES_RG_INPUT(8, "v33", "%[x8]") FES_RG_INPUT(9, "v34", "%[x9]")         \
+    FES_RG_INPUT(10, "v35", "%[x10]")                                                                      \
+    "s_cmp_eq_u32 %[n], 11\n"                                                                             \
+    "s_cbranch_scc1 fes_rg_in_done_%=\n"                                                                  \
+    "s_mov_b32 s63, 11\n"                                                                                \
+    "fes_rg_in_loop_%=:\n"                                                                                \
+    "s_sub_u32 s62, s63, 5\n"                                                                           \
+    "s_lshr_b64 s[96:97], %[base], s62\n"                                                                \
+    "s_and_b32 s96, s96, 1\n"                                                                             \
+    "s_sub_u32 s96, 0, s96\n"                                                                             \
+    "s_add_u32 s97, s63, 1\n"                                                                            \
+    "s_set_gpr_idx_on s97, gpr_idx(DST)\n"                                                                \
+    "v_mov_b32 v24, s96\n"                                                                                \
+    "s_set_gpr_idx_off\n"                                                                                 \
+    "s_add_u32 s63, s63, 1\n"                                                                           \
+    "s_cmp_lt_u32 s63, %[n]\n"                                                                           \
+    "s_cbranch_scc1 fes_rg_in_loop_%=\n"                                                                  \
+    "fes_rg_in_done_%=:\n"                                                                                \
+    "v_mov_b32 %[m], 0\n"                                                                                 \
+    "s_mov_b64 s[98:99], %[prog]\n"                                                                       \
+    "s_mov_b32 s62, %[nb]\n"                                                                             \
+    "s_load_dwordx16 s[64:79], s[98:99], 0x0\n"                                                           \
+    "fes_rg_loop_%=:\n"                                                                                   \
+    "s_waitcnt lgkmcnt(0)\n"                                                                              \
+    "s_sub_u32 s62, s62, 1\n"                                                                           \
+    "s_cmp_eq_u32 s62, 0\n"                                                                              \
+    "s_cbranch_scc1 fes_rg_lasta_%=\n"                                                                    \
+    "s_add_u32 s98, s98, 64\n"                                                                            \
+    "s_addc_u32 s99, s99, 0\n"                                                                            \
+    "s_load_dwordx16 s[80:95], s[98:99], 0x0\n"                                                           \
+    "fes_rg_lasta_%=:\n"                                                                                  \
+    FES_RG_BUF_A                                                                                          \
+    "s_cmp_eq_u32 s62, 0\n"                                                                              \
+    "s_cbranch_scc1 fes_rg_end_%=\n"                                                                      \
+    "s_waitcnt lgkmcnt(0)\n"                                                                              \
+    "s_sub_u32 s62, s62, 1\n"                                                                           \
+    "s_cmp_eq_u32 s62, 0\n"                                                                              \
+    "s_cbranch_scc1 fes_rg_lastb_%=\n"                                                                    \
+    "s_add_u32 s98, s98, 64\n"                                                                            \
+    "s_addc_u32 s99, s99, 0\n"                                                                            \
+    "s_load_dwordx16 s[64:79], s[98:99], 0x0\n"                                                           \
+    "fes_rg_lastb_%=:\n"                                                                                  \
+    FES_RG_BUF_B                                                                                          \
+    "s_cmp_eq_u32 s62, 0\n"                                                                              \
+    "s_cbranch_scc0 fes_rg_loop_%=\n"                                                                     \
+    "fes_rg_end_%=:\n"
+
+#define FES_RG_SCLOB                                                                                      \
+    "m0", "scc", "s62", "s63", "s64", "s65", "s66", "s67", "s68", "s69", "s70", "s71", "s72", "s73", "s74", "s75", "s76",  \
+        "s77", "s78", "s79", "s80", "s81", "s82", "s83", "s84", "s85", "s86", "s87", "s88", "s89", "s90",   \
+        "s91", "s92", "s93", "s94", "s95", "s96", "s97", "s98", "s99"
+#define FES_V10(d) "v" #d "0", "v" #d "1", "v" #d "2", "v" #d "3", "v" #d "4", "v" #d "5", "v" #d "6", \
+                   "v" #d "7", "v" #d "8", "v" #d "9"
+// v16..v119 (file rows 0..95)
+#define FES_RG_VCLOB_96                                                                                   \
+    "v16", "v17", "v18", "v19", FES_V10(2), FES_V10(3), FES_V10(4), FES_V10(5), FES_V10(6), FES_V10(7),     \
+        FES_V10(8), FES_V10(9), FES_V10(10), FES_V10(11)
+// v16..v159 (file rows 0..135)
+#define FES_RG_VCLOB_136 FES_RG_VCLOB_96, FES_V10(12), FES_V10(13), FES_V10(14), FES_V10(15)
+// v16..v255 (file rows 0..231)
+#define FES_RG_VCLOB_232 FES_RG_VCLOB_136, FES_V10(16), FES_V10(17), FES_V10(18), FES_V10(19), FES_V10(20), \
+                         FES_V10(21), FES_V10(22), FES_V10(23), FES_V10(24), "v250", "v251", "v252", "v253",   \
+                         "v254", "v255"
+
+template <int R>
+__device__ __forceinline__ uint32_t regs_pass(const Instr* prog, uint32_t nb, uint32_t n, uint64_t base,
+                                              uint32_t x5, uint32_t x6, uint32_t x7, uint32_t x8, uint32_t x9,
+                                              uint32_t x10) {
+    uint32_t m;
+#define FES_RG_OPERANDS                                                                                   \
+    : [m] "=&v"(m)                                                                                        \
+    : [prog] "s"(prog), [nb] "s"(nb), [n] "s"(n), [base] "s"(base), [x5] "v"(x5), [x6] "v"(x6),            \
+      [x7] "v"(x7), [x8] "v"(x8), [x9] "v"(x9), [x10] "v"(x10)
+    if constexpr (R == 96) {
+        asm volatile(FES_RG_PASS_ASM FES_RG_OPERANDS : FES_RG_SCLOB, FES_RG_VCLOB_96);
+    } else if constexpr (R == 136) {
+        asm volatile(FES_RG_PASS_ASM FES_RG_OPERANDS : FES_RG_SCLOB, FES_RG_VCLOB_136);
+    } else {
+        asm volatile(FES_RG_PASS_ASM FES_RG_OPERANDS : FES_RG_SCLOB, FES_RG_VCLOB_232);
+    }
+#undef FES_RG_OPERANDS
+    return m;
+}
+
+// One wave per workgroup; waves_per_eu pins the occupancy the file size allows.
+template <int R, int kWaves>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWaves, kWaves)))
+es_interp_regs_kernel(InterpLaunch L) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t x5 = 0u - (lane & 1u), x6 = 0u - ((lane >> 1) & 1u), x7 = 0u - ((lane >> 2) & 1u);
+    const uint32_t x8 = 0u - ((lane >> 3) & 1u), x9 = 0u - ((lane >> 4) & 1u), x10 = 0u - ((lane >> 5) & 1u);
+    const uint32_t wave_gid = blockIdx.x;
+    const uint32_t waves = gridDim.x;
+    const uint32_t nclaim = waves < kClaimCounters ? waves : kClaimCounters;
+    const uint32_t claim = __builtin_amdgcn_readfirstlane(wave_gid % nclaim);
+    unsigned long long* const counter = &L.ctl->next_item[claim * kClaimStride];
+    for (;;) {
+        const uint64_t k = uniform64(atomicAdd(counter, lane == 0 ? 1ull : 0ull));
+        const uint64_t item = claim + k * nclaim;
+        if (item >= L.total_items) break;
+        if (L.cancel && __builtin_amdgcn_readfirstlane(
+                            __hip_atomic_load(L.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)))
+            break;
+        const FES_CONST ConeDesc* cones = as_const(L.cones);
+        uint32_t lo = 0, hi = L.num_cones - 1;
+        while (lo < hi) {
+            uint32_t mid = (lo + hi + 1) >> 1;
+            if (cones[mid].item_begin <= item) lo = mid; else hi = mid - 1;
+        }
+        const FES_CONST ConeDesc* c = cones + lo;
+        unsigned long long* best = &L.best[c->best_index];
+        const uint64_t hw_begin = c->hw_begin, hw_end = c->hw_end;
+        const uint64_t hw0 = c->hw_first + (item - c->item_begin) * c->tile_hw;
+        const uint64_t hw_stop = min(hw0 + c->tile_hw, hw_end);
+        const uint32_t n = __builtin_amdgcn_readfirstlane(c->n_inputs);
+        const uint32_t nb = __builtin_amdgcn_readfirstlane(c->n_instr / 4u);
+        const Instr* prog = c->prog;
+        const uint64_t best_now = uniform64(__hip_atomic_load(best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        for (uint64_t base = hw0; base < hw_stop; base += 64u) {
+            if (32u * base >= best_now) break;
+            const uint32_t mw = nb ? regs_pass<R>(prog, nb, n, base, x5, x6, x7, x8, x9, x10) : 0u;
+            const uint64_t hw = base + lane;
+            const uint32_t mj = (hw >= hw_begin && hw < hw_end) ? mw : 0u;
+            const uint64_t bal = __ballot(mj != 0u);
+            if (bal) {
+                const uint32_t l = (uint32_t)__builtin_ctzll(bal);
+                const uint32_t ml = __builtin_amdgcn_readlane(mj, l);
+                atomicMin(best, 32ull * (base + l) + (uint32_t)__builtin_ctz(ml));
+                break;
+            }
+        }
+    }
+}
+
+template <int R, int kWaves>
+hipError_t launch_regs(const InterpLaunch& L, int grid, hipStream_t stream) {
+    hipLaunchKernelGGL((es_interp_regs_kernel<R, kWaves>), dim3(grid), dim3(64), 0, stream, L);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+int interp_regs_rows(uint32_t rows, int* waves_per_simd) {
+    int w = 0, r = 0;
+    if (rows <= 96) { r = 96; w = 4; }
+    else if (rows <= 136) { r = 136; w = 3; }
+    else if (rows <= 232) { r = 232; w = 2; }
+    if (waves_per_simd) *waves_per_simd = w;
+    return r;
+}
+
+hipError_t launch_interp_regs(const InterpLaunch& L, int regs, int grid, hipStream_t stream) {
+    if (L.num_cones == 0 || grid <= 0 || L.rows_max > (uint32_t)regs) return hipErrorInvalidValue;
+    switch (regs) {
+        case 96: return launch_regs<96, 4>(L, grid, stream);
+        case 136: return launch_regs<136, 3>(L, grid, stream);
+        case 232: return launch_regs<232, 2>(L, grid, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 size_t interp_lds_bytes(uint32_t rows, int K, int waves_per_block) {
     return (size_t)waves_per_block * rows * 64u * (size_t)K * sizeof(uint32_t);

@@ -74,6 +74,12 @@ hipError_t launch_interp_sim(const InterpLaunch& L, int K, int B, bool lds, int 
 hipError_t launch_signature_hash(const uint32_t* sig, uint64_t rows, uint64_t words, uint64_t* hash,
                                  uint64_t* ones, int grid, hipStream_t stream);
 
+// Register tier: value files in VGPRs (one wave per workgroup, bundles of 4, one 32-bit word per
+// lane).  interp_regs_rows: the file size (96, 136 or 232 rows) that holds `rows`, 0 if none
+// does, with the waves per SIMD it allows.  launch_interp_regs: `regs` is that file size.
+int interp_regs_rows(uint32_t rows, int* waves_per_simd);
+hipError_t launch_interp_regs(const InterpLaunch& L, int regs, int grid, hipStream_t stream);
+
 // Largest per-workgroup dynamic LDS the interpreter may request.
 size_t interp_lds_bytes(uint32_t rows, int K, int waves_per_block);
 

@@ -4,24 +4,31 @@
 
 namespace fes {
 
-// Fitted on one MI355X by least squares on relative error (plain checks of 32 cones, n 12..32):
-// median relative error 8% (interpreter), 16% (specialized), 1% (compile); largest 28%, 61%,
-// 4%.  Interpreter gates are the instructions of its bundled stream (three-AND XORs count once).
+// Fitted on one MI355X by least squares on relative error (plain checks of 37 seeded cones and the
+// multiplier and MAC miters, n 12..32; paper_2512_06627_amd/calibrate.py): median (largest)
+// relative error 3% (15%) interpreter, 17% (60%) specialized, 6% (12%) compile.  Interpreter gates are
+// the instructions of its bundled stream (three-AND XORs count once); its rate depends on the tier
+// that holds the value file.
 namespace model {
-constexpr double kInterpT0Ms = 0.0169;
-constexpr uint32_t kInterpSlotsBreak = 140;      // rate drops above: fewer waves per CU
-constexpr double kInterpRate = 4.62e13;          // gate instructions*patterns/s, value files of <= break slots
-constexpr double kInterpRateLarge = 2.71e13;     // above
-constexpr double kInterpMsPerGateFloor = 5.0e-5; // one wave pass per gate: spaces below a chip's waves
-constexpr double kSpecT0Ms = 0.0130;
-constexpr double kSpecLutPassesPerS = 6.33e11;
-constexpr double kCompileC0Ms = 104.1;
-constexpr double kCompileMsPerLut = 0.00649;
+constexpr double kInterpT0Ms = 0.0140;
+constexpr uint32_t kTierRows[3] = {96, 136, 232};  // register tier files; LDS or device memory above
+constexpr double kInterpRate[4] = {1.092e14, 1.135e14, 9.48e13, 2.18e13};  // gate instructions*patterns/s
+constexpr double kInterpMsPerGateFloor = 3.98e-5; // one wave pass per gate: spaces below a chip's waves
+constexpr double kSpecT0Ms = 0.0135;
+constexpr double kSpecLutPassesPerS = 6.36e11;
+constexpr double kCompileC0Ms = 118.4;
+constexpr double kCompileMsPerLut = 0.00685;
 constexpr double kLutsPerGate = 0.30;
 }  // namespace model
 
-double model_interp_ms(uint32_t gates, uint32_t slots, double patterns) {
-    const double rate = slots > model::kInterpSlotsBreak ? model::kInterpRateLarge : model::kInterpRate;
+int model_interp_tier(uint32_t rows) {
+    for (int t = 0; t < 3; ++t)
+        if (rows <= model::kTierRows[t]) return t;
+    return 3;
+}
+
+double model_interp_ms(uint32_t gates, uint32_t rows, double patterns) {
+    const double rate = model::kInterpRate[model_interp_tier(rows)];
     return model::kInterpT0Ms + (double)gates * std::max(patterns / rate * 1e3, model::kInterpMsPerGateFloor);
 }
 
@@ -35,15 +42,15 @@ uint32_t model_lut_steps_estimate(uint32_t and_gates) {
     return (uint32_t)((double)and_gates * model::kLutsPerGate + 0.5);
 }
 
-double lpt_cost_ms(uint32_t interp_gates, uint32_t slots, double patterns) {
-    return model_interp_ms(interp_gates, slots, patterns);
+double lpt_cost_ms(uint32_t interp_gates, uint32_t rows, double patterns) {
+    return model_interp_ms(interp_gates, rows, patterns);
 }
 
 double server_compile_threshold_ms() { return kTierCompileFactor * model_compile_ms(0); }
 
 bool server_wants_compile(const TierJob& j, size_t sharing, double* remaining_ms, double* compile_ms) {
     const double t_interp = (double)std::max<size_t>(1, sharing) *
-                            model_interp_ms(std::max<uint32_t>(1, j.interp_gates), j.slots, j.remaining_patterns);
+                            model_interp_ms(std::max<uint32_t>(1, j.interp_gates), j.rows, j.remaining_patterns);
     const double t_compile = model_compile_ms(j.lut_steps);
     if (remaining_ms) *remaining_ms = t_interp;
     if (compile_ms) *compile_ms = t_compile;

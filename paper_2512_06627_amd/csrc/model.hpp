@@ -12,10 +12,14 @@
 namespace fes {
 
 //  interpreter:  t = t0 + N * max(patterns / R, L), N = bundled-stream gate instructions,
-//                R by value-file size (S slots), L = one wave pass per gate
+//                R by the value-file tier of its `rows` (register tier files of at most 96,
+//                136 and 232 rows at four, three and two waves per SIMD; LDS or device memory
+//                above), L = one wave pass per gate
 //  specialized:  t = t0 + LUT steps * passes / R, passes = patterns / 2048 (at least 1)
 //  compile:      t = c0 + c1 * LUT steps
-double model_interp_ms(uint32_t gates, uint32_t slots, double patterns);
+double model_interp_ms(uint32_t gates, uint32_t rows, double patterns);
+// Tier of a value file of `rows` rows: 0..2 register tier (96, 136, 232 rows), 3 LDS or device memory.
+int model_interp_tier(uint32_t rows);
 double model_specialized_ms(uint32_t lut_steps, double patterns);
 double model_compile_ms(uint32_t lut_steps);
 
@@ -26,7 +30,7 @@ uint32_t model_lut_steps_estimate(uint32_t and_gates);
 
 // Longest-processing-time cost of a cone in a shared interpreter launch: its predicted
 // interpreter time over its range (ms).
-double lpt_cost_ms(uint32_t interp_gates, uint32_t slots, double patterns);
+double lpt_cost_ms(uint32_t interp_gates, uint32_t rows, double patterns);
 
 // The server's specialized tier: a job on the interpreter shares each step equally with the
 // other `sharing` interpreter jobs, so its remaining time there is `sharing` times its
@@ -37,7 +41,7 @@ double lpt_cost_ms(uint32_t interp_gates, uint32_t slots, double patterns);
 // one compile thread.
 struct TierJob {
     uint32_t interp_gates = 1;  // bundled-stream gate instructions
-    uint32_t slots = 0;         // peak live slots (value-file size)
+    uint32_t rows = 0;          // value-file rows of the interpreter's stream (its tier)
     uint32_t lut_steps = 0;     // exact when the LUT program exists, else the estimate
     double remaining_patterns = 0;
 };

@@ -54,18 +54,17 @@ void noalloc_setup(Device& dev) {
 uint64_t noalloc_check(Device& dev, Circuit& c, const fastlec_es_options& o, const HwRange& r, hipStream_t stream,
                        double* ms) {
     if (!dev.noalloc_scratch) throw Error{kErrDevice, "no-allocation scratch array has no device address"};
-    // Size limit first (bundles of 16 gates, of 8 with four words per lane, as the schedule
-    // picks them), then the LDS fit of the value file.
-    const uint32_t B = o.words_per_thread == 4 ? 8u : 16u;
-    const Plan& p = c.plan_for(B);
+    // The schedule of a plain check, then the size limit of its stream, then the tier: value
+    // files in VGPRs or LDS only.
+    std::vector<Circuit*> one{&c};
+    const Schedule sch = default_schedule(dev, one, &o);
+    const Plan& p = c.plan_for((uint32_t)sch.B);
     const size_t prog_bytes = p.prog.size() * sizeof(Instr);
     if (kProgOff + prog_bytes > kScratchBytes)
         throw Error{kErrInvalid, "instruction stream of " + std::to_string(p.prog.size()) +
                                      " instructions exceeds the no-allocation scratch (at most " +
                                      std::to_string((kScratchBytes - kProgOff) / sizeof(Instr)) + ")"};
-    std::vector<Circuit*> one{&c};
-    const Schedule sch = default_schedule(dev, one, &o);
-    if (!sch.lds || (uint32_t)sch.B != B)
+    if (!sch.lds && !sch.regs)
         throw Error{kErrInvalid, "value file does not fit in LDS with this schedule; the no-allocation entry point "
                                  "has no device-memory value files"};
     std::lock_guard<std::mutex> g(dev.noalloc_mu);
@@ -95,7 +94,7 @@ uint64_t noalloc_check(Device& dev, Circuit& c, const fastlec_es_options& o, con
     FES_HIP(hipMemcpyAsync(base, head.bytes, sizeof(head.bytes), hipMemcpyHostToDevice, stream));
     if (prog_bytes)
         FES_HIP(hipMemcpyAsync(base + kProgOff, p.prog.data(), prog_bytes, hipMemcpyHostToDevice, stream));
-    FES_HIP(launch_interp(L, s.K, s.B, true, s.grid, s.block, stream));
+    FES_HIP(launch_schedule(L, s, stream));
     FES_HIP(hipMemcpyAsync(&best, base + kBestOff, 8, hipMemcpyDeviceToHost, stream));
     FES_HIP(hipStreamSynchronize(stream));
     if (ms) *ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

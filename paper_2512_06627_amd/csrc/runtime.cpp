@@ -228,6 +228,33 @@ int max_waves_per_cu(const Device&) { return 32; }
 
 }  // namespace
 
+bool regs_tier_enabled() {
+    static const bool on = [] {
+        const char* v = std::getenv("FASTLEC_ES_INTERP_REGS");
+        return !(v && std::atoi(v) == 0);
+    }();
+    return on;
+}
+
+bool make_schedule_regs(Device& dev, uint32_t rows, Schedule& s) {
+    int waves = 0;
+    const int regs = interp_regs_rows(rows, &waves);
+    if (!regs || !regs_tier_enabled()) return false;
+    s = Schedule{};
+    s.K = 1;
+    s.B = 4;
+    s.block = 64;
+    s.lds = false;
+    s.regs = regs;
+    s.grid = dev.prop.multiProcessorCount * 4 * waves;  // `waves` one-wave workgroups per SIMD
+    return true;
+}
+
+hipError_t launch_schedule(const InterpLaunch& L, const Schedule& sch, hipStream_t stream) {
+    if (sch.regs) return launch_interp_regs(L, sch.regs, sch.grid, stream);
+    return launch_interp(L, sch.K, sch.B, sch.lds, sch.grid, sch.block, stream);
+}
+
 bool make_schedule(Device& dev, const std::vector<Circuit*>& cs, int K, int B, int block, bool lds, Schedule& s) {
     return make_schedule_rows(dev, rows_for(cs, B), K, B, block, lds, s);
 }
@@ -261,6 +288,9 @@ Schedule default_schedule(Device& dev, const std::vector<Circuit*>& cs, const fa
     if (K0 != 1 && K0 != 2 && K0 != 4) throw Error{kErrInvalid, "words_per_thread must be 1, 2 or 4"};
     if (block0 < 64 || block0 > 1024 || block0 % 64) throw Error{kErrInvalid, "wg_size must be a multiple of 64 in [64, 1024]"};
     Schedule s;
+    // Value files in VGPRs when they fit and the caller fixes no other schedule: two to four
+    // waves per SIMD instead of the one that LDS files allow.
+    if (!hbm && !fix_k && !fix_block && make_schedule_regs(dev, rows_for(cs, 4), s)) return s;
     if (!hbm) {
         // Value files in LDS: the interpreter is latency-bound, so take the words per lane and
         // workgroup size that keep the most pattern words in flight per CU (waves x K), with
@@ -319,7 +349,7 @@ uint64_t build_descs(Device& dev, const std::vector<Circuit*>& cs, const std::ve
     std::iota(order.begin(), order.end(), 0);
     std::vector<double> cost(k);
     for (size_t i = 0; i < k; ++i)
-        cost[i] = lpt_cost_ms(cs[i]->interp_gates(), cs[i]->plan1.peak_slots,
+        cost[i] = lpt_cost_ms(cs[i]->interp_gates(), cs[i]->interp_rows(),
                               32.0 * (double)(ranges[i].end - ranges[i].begin));
     std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
     uint64_t item = 0;
@@ -371,7 +401,7 @@ void run_interp(Device& dev, const std::vector<Circuit*>& cs, const std::vector<
     const size_t k = cs.size();
     const uint32_t rows_max = rows_for(cs, sch.B);
     const size_t waves = (size_t)sch.grid * (sch.block / 64);
-    const size_t file_bytes = sch.lds ? 0 : waves * rows_max * 64ull * sch.K * 4ull;
+    const size_t file_bytes = (sch.lds || sch.regs) ? 0 : waves * rows_max * 64ull * sch.K * 4ull;
     Layout lay = layout(k, file_bytes);
     if (mem.ptr) check_dev_mem(mem, lay.total);
     // With caller memory the pool only supplies the pinned staging of the control block.
@@ -397,7 +427,7 @@ void run_interp(Device& dev, const std::vector<Circuit*>& cs, const std::vector<
     L.total_items = items;
     L.ctl = (LaunchCtl*)devp;
     L.best = (unsigned long long*)(devp + lay.best_off);
-    L.hbm_rows = sch.lds ? nullptr : (uint32_t*)(devp + lay.files_off);
+    L.hbm_rows = (sch.lds || sch.regs) ? nullptr : (uint32_t*)(devp + lay.files_off);
     L.cancel = cancel;
 
     hipEvent_t e0, e1;
@@ -411,10 +441,11 @@ void run_interp(Device& dev, const std::vector<Circuit*>& cs, const std::vector<
         }
     } ev{e0, e1};
     trace("interp launch: %zu cones, %llu items, K=%d B=%d %s grid=%d block=%d rows=%u", k,
-          (unsigned long long)items, sch.K, sch.B, sch.lds ? "lds" : "hbm", sch.grid, sch.block, rows_max);
+          (unsigned long long)items, sch.K, sch.B, sch.regs ? "regs" : sch.lds ? "lds" : "hbm", sch.grid, sch.block,
+          rows_max);
     FES_HIP(hipMemcpyAsync(devp, host, lay.files_off, hipMemcpyHostToDevice, stream));
     FES_HIP(hipEventRecord(e0, stream));
-    FES_HIP(launch_interp(L, sch.K, sch.B, sch.lds, sch.grid, sch.block, stream));
+    FES_HIP(launch_schedule(L, sch, stream));
     FES_HIP(hipEventRecord(e1, stream));
     FES_HIP(hipMemcpyAsync(hbest, devp + lay.best_off, 8 * k, hipMemcpyDeviceToHost, stream));
     FES_HIP(hipStreamSynchronize(stream));

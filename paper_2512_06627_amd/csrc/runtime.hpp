@@ -88,6 +88,8 @@ struct Circuit {
     std::map<std::pair<int, uint32_t>, Instr*> dev_sim_prog;              // (device, bundle) -> stream
     ~Circuit();
     const LutProgram& lut_program();
+    // Value-file rows of the interpreter's stream in bundles of 4 (the runtime model's tier).
+    uint32_t interp_rows() { return plan_for(4).rows; }
     // LUT steps of the specialized program if it is built, else the model's estimate (never
     // builds it).
     uint32_t lut_steps_known();
@@ -138,7 +140,14 @@ struct Schedule {
     uint64_t tile_hw = 0;  // 0 = derived
     bool lds = true;
     int grid = 0;          // 0 = derived (persistent: fill the chip)
+    int regs = 0;          // register tier: value-file rows in VGPRs (K 1, B 4, one wave per workgroup)
 };
+// Launch the interpreter kernel a schedule names (register, LDS or device-memory tier).
+hipError_t launch_schedule(const InterpLaunch& L, const Schedule& sch, hipStream_t stream);
+// Register-tier schedule for value files of `rows` rows; false when none holds them or the
+// tier is switched off (FASTLEC_ES_INTERP_REGS=0).
+bool make_schedule_regs(Device& dev, uint32_t rows, Schedule& out);
+bool regs_tier_enabled();
 
 struct CheckOut {
     uint64_t best = ~0ull;

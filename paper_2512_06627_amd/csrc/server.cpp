@@ -200,7 +200,7 @@ void fastlec_es_server::plan_tiers(const std::vector<Job*>& act) {
         // only built here (host time) when the remaining time could pay for a compile at all.
         TierJob tj;
         tj.interp_gates = j->c->interp_gates();
-        tj.slots = j->c->plan1.peak_slots;
+        tj.rows = j->c->interp_rows();
         tj.remaining_patterns = 32.0 * (double)(j->range.end - j->cursor);
         tj.lut_steps = 0;
         double remaining_ms = 0;
@@ -292,7 +292,10 @@ void fastlec_es_server::step(const std::vector<Job*>& act) {
         o.kernel = g.lds ? FASTLEC_KERNEL_INTERP : FASTLEC_KERNEL_INTERP_HBM;
         o.words_per_thread = kK;
         bool have = false;
-        if (g.lds && server_occupancy() && !opts.wg_size) {
+        // Value files in VGPRs when every job of the group fits (bundles of 4).
+        if (g.lds && !opts.wg_size && !opts.words_per_thread && make_schedule_regs(*dev, rows_for(*g.c, 4), g.sch))
+            have = true;
+        if (!have && g.lds && server_occupancy() && !opts.wg_size) {
             int best = -1;
             for (int block : {256, 128, 64}) {
                 Schedule t;
@@ -344,13 +347,13 @@ void fastlec_es_server::step(const std::vector<Job*>& act) {
         InterpLaunch L;
         L.cones = (const ConeDesc*)(devp + g.desc_off);
         L.num_cones = (uint32_t)g.c->size();
-        L.rows_max = rows_for(*g.c, kB);
+        L.rows_max = rows_for(*g.c, g.sch.B);
         L.total_items = g.items;
         L.ctl = (LaunchCtl*)(devp + g.ctl_off);
         L.best = (unsigned long long*)(devp + off_best);
         L.hbm_rows = g.sch.lds ? nullptr : (uint32_t*)files.dev;
         L.cancel = nullptr;
-        FES_HIP(launch_interp(L, g.sch.K, g.sch.B, g.sch.lds, g.sch.grid, g.sch.block, stream));
+        FES_HIP(launch_schedule(L, g.sch, stream));
     }
     FES_HIP(hipEventRecord(e1.e, stream));
     // Specialized slices: own claim counter per slot (zeroed first), shared best[] entry.
@@ -425,7 +428,7 @@ void fastlec_es_server::loop() {
                         j->t_admit = now;
                         // The model's ETA: the job's interpreter time alone, times the jobs that
                         // share the device with it at admission (itself included).
-                        j->res.predicted_ms = model_interp_ms(j->c->interp_gates(), j->c->plan1.peak_slots,
+                        j->res.predicted_ms = model_interp_ms(j->c->interp_gates(), j->c->interp_rows(),
                                                               32.0 * (double)(j->range.end - j->range.begin)) *
                                               (double)(active.size() + 1);
                         st.charge_in_use_bytes += j->charge;

@@ -1,7 +1,8 @@
 """The runtime-model fit (paper_2512_06627_amd/calibrate.py) recovers known constants.
 
 Times are generated from the model's own form with chosen constants (interpreter: launch
-cost, two rates split at ROWS_BREAK slots, a per-gate floor; specialized: launch cost and a
+cost, one rate per value-file tier (register tier files of 96, 136, 232 rows, LDS above), a
+per-gate floor; specialized: launch cost and a
 rate over LUT steps x passes; compile: fixed plus per-LUT cost) and perturbed by a seeded 3%
 noise; the fit must return the constants within a few percent.  No GPU involved.
 """
@@ -12,28 +13,31 @@ from paper_2512_06627_amd import calibrate
 
 def synthetic(seed=7):
     rng = np.random.default_rng(seed)
-    t0, r_lo, r_hi, floor = 0.02, 5e13, 3e13, 4e-5
+    t0, floor = 0.02, 4e-5
+    rates = {0: 1.4e14, 1: 1.1e14, 2: 8e13, 3: 3e13}
     s0, s_rate, c0, c1 = 0.013, 6e11, 105.0, 0.0065
     rows = []
     for n in (12, 14, 16, 18, 20, 22, 24, 26, 28):
-        for N in (300, 1000, 3000, 8000):
-            slots = 40 + N // 60
+        for N in (300, 1000, 3000, 8000, 14000):
+            slots = 40 + N // 50
             luts = N // 3
             P = 2.0 ** n
-            ti = t0 + N * max(P / (r_hi if slots > calibrate.ROWS_BREAK else r_lo) * 1e3, floor)
+            ti = t0 + N * max(P / rates[calibrate.tier(slots)] * 1e3, floor)
             ts = s0 + luts * max(1.0, P / 2048.0) / s_rate * 1e3
             tc = c0 + c1 * luts
             noise = lambda: 1.0 + 0.03 * rng.standard_normal()
             rows.append({"name": f"n{n}_{N}", "n": n, "N": N, "rows": slots, "luts": luts,
                          "interp_ms": ti * noise(), "specialized_ms": ts * noise(), "compile_ms": tc * noise()})
-    return rows, dict(t0=t0, r_lo=r_lo, r_hi=r_hi, floor=floor, s0=s0, s_rate=s_rate, c0=c0, c1=c1)
+    return rows, dict(t0=t0, rates=rates, floor=floor, s0=s0, s_rate=s_rate, c0=c0, c1=c1)
 
 
 def test_fit_recovers_constants():
     rows, k = synthetic()
     f = calibrate.fit(rows)
-    assert abs(f["interp_node_patterns_per_s"] / k["r_lo"] - 1) < 0.05
-    assert abs(f["interp_node_patterns_per_s_above_break"] / k["r_hi"] - 1) < 0.05
+    got = f["interp_gate_patterns_per_s_by_tier"]
+    assert sorted(got) == sorted(k["rates"])  # every tier has data
+    for t, r in k["rates"].items():
+        assert abs(got[t] / r - 1) < 0.05, (t, got[t], r)
     assert abs(f["interp_ms_per_gate_floor"] / k["floor"] - 1) < 0.15  # grid of 61 points per decade band
     assert abs(f["specialized_lut_passes_per_s"] / k["s_rate"] - 1) < 0.05
     assert abs(f["compile_c0_ms"] / k["c0"] - 1) < 0.05

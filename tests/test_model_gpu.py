@@ -41,7 +41,7 @@ def test_batch_routes_large_cones_to_specialized_kernel():
     E = es()
     gs = [miters.layered_cone_miter(60 + i, 14 + i % 3, 300) for i in range(6)]
     gs += [miters.mult_miter(12, "booth"), miters.mult_miter(12, "booth", fault_seed=3),
-           miters.layered_cone_miter(72, 30, 6000), miters.layered_cone_miter(73, 31, 4000, fault_seed=2)]
+           miters.layered_cone_miter(72, 33, 6000), miters.layered_cone_miter(73, 33, 4000, fault_seed=2)]
     cs = [E.fastlec_es_load_aig(g.to_aig()) for g in gs]
     res = E.fastlec_es_check_batch(cs)
     want_spec = []
@@ -83,7 +83,7 @@ def test_batch_runs_large_interpreter_cones_alone():
     oracle's for the small ones), and the large cones report their own kernel times."""
     E = es()
     small = [miters.layered_cone_miter(120 + i, 12 + i % 5, 400, fault_seed=(i if i % 2 else None)) for i in range(6)]
-    large = [miters.layered_cone_miter(130 + i, 25 + i % 2, 3000, fault_seed=(7 if i == 1 else None)) for i in range(3)]
+    large = [miters.layered_cone_miter(130 + i, 27 + i % 2, 3000, fault_seed=(7 if i == 1 else None)) for i in range(3)]
     gs = small + large
     cs = [E.fastlec_es_load_aig(g.to_aig()) for g in gs]
     preds = [E.fastlec_es_predict(c)["interp_ms"] for c in cs]
