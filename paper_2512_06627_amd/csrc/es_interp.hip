@@ -263,82 +263,100 @@ hipError_t launch_k(const InterpLaunch& L, int B, bool lds, int grid, int block,
 // Row r of the file is v[kFileBase + r]; rows are read and written through gfx950's GPR index
 // mode (s_set_gpr_idx_on / _idx / _off: the low 8 bits of an SGPR offset the register number of
 // the indexed operand), so the file needs no address arithmetic.  The index is taken from the
-// instruction words themselves: only their low 8 bits count, so a row with its complement flag
-// in bit 31 indexes the right register.  Bundles of four gates keep the stream's
-// read-all-then-write-all semantics: the eight operands go to v16..v23, the four results are
-// computed and written back.  The instruction stream comes in by scalar loads, one bundle
-// (64 bytes) ahead into a second set of SGPRs; with no LDS operations in the pass, the scalar
-// wait counter tracks only those loads.
+// operand and destination words themselves: only their low 8 bits count, so a row with its
+// complement flag (or the bundle's output mark) in bit 31 indexes the right register.  Bundles
+// of four gates keep the stream's read-all-then-write-all semantics: the eight operands go to
+// v16..v23, the four results are computed and written back.  The stream is the register tier's
+// own encoding (encode_regs_stream: complement and XOR masks precomputed, one output mark per
+// bundle), so a gate costs no scalar instruction besides its three index moves.  It comes in by
+// scalar loads, one bundle (112 bytes) ahead into a second set of SGPRs; with no LDS operations
+// in the pass, the scalar wait counter tracks only those loads.
 //
 // One pass (2,048 patterns: 64 lanes x 32) is one asm statement.  It owns v16..v(kFileBase+R-1),
-// s62..s99 and m0.  Inputs: the stream, the bundle count, n, the pass's first half-word index
+// s36..s99 and m0.  Inputs: the stream, the bundle count, n, the pass's first half-word index
 // (bits 6 and up give inputs 11 and up) and the lane words of inputs 5..10.  Output: the lane's
 // miter word.
 constexpr int kFileBase = 24;
 
-#define FES_RG_READS(X0, X1, X4, X5, X8, X9, X12, X13)           \
-    "s_set_gpr_idx_on " X0 ", gpr_idx(SRC0)\n"                   \
-    "v_mov_b32 v16, v24\n"                                        \
-    "s_set_gpr_idx_idx " X1 "\n"                                  \
-    "v_mov_b32 v17, v24\n"                                        \
-    "s_set_gpr_idx_idx " X4 "\n"                                  \
-    "v_mov_b32 v18, v24\n"                                        \
-    "s_set_gpr_idx_idx " X5 "\n"                                  \
-    "v_mov_b32 v19, v24\n"                                        \
-    "s_set_gpr_idx_idx " X8 "\n"                                  \
-    "v_mov_b32 v20, v24\n"                                        \
-    "s_set_gpr_idx_idx " X9 "\n"                                  \
-    "v_mov_b32 v21, v24\n"                                        \
-    "s_set_gpr_idx_idx " X12 "\n"                                 \
-    "v_mov_b32 v22, v24\n"                                        \
-    "s_set_gpr_idx_idx " X13 "\n"                                 \
-    "v_mov_b32 v23, v24\n"                                        \
+// Eight operand reads of a bundle (a0, b0, ..., a3, b3 into v16..v23) through the SRC0 index.
+#define FES_RG_READS(A0, B0, A1, B1, A2, B2, A3, B3) \
+    "s_set_gpr_idx_on " A0 ", gpr_idx(SRC0)\n"       \
+    "v_mov_b32 v16, v24\n"                            \
+    "s_set_gpr_idx_idx " B0 "\n"                      \
+    "v_mov_b32 v17, v24\n"                            \
+    "s_set_gpr_idx_idx " A1 "\n"                      \
+    "v_mov_b32 v18, v24\n"                            \
+    "s_set_gpr_idx_idx " B1 "\n"                      \
+    "v_mov_b32 v19, v24\n"                            \
+    "s_set_gpr_idx_idx " A2 "\n"                      \
+    "v_mov_b32 v20, v24\n"                            \
+    "s_set_gpr_idx_idx " B2 "\n"                      \
+    "v_mov_b32 v21, v24\n"                            \
+    "s_set_gpr_idx_idx " A3 "\n"                      \
+    "v_mov_b32 v22, v24\n"                            \
+    "s_set_gpr_idx_idx " B3 "\n"                      \
+    "v_mov_b32 v23, v24\n"                            \
     "s_set_gpr_idx_off\n"
-// gate u: operands in TA/TB, instruction words A (a), B (b), F (flags); result left in TA
-#define FES_RG_GATE(TA, TB, A, B, F, LBL)                        \
-    "s_ashr_i32 s96, " A ", 31\n"                                 \
-    "v_xor_b32 " TA ", s96, " TA "\n"                             \
-    "s_ashr_i32 s96, " B ", 31\n"                                 \
-    "v_xor_b32 " TB ", s96, " TB "\n"                             \
-    "s_bfe_i32 s96, " F ", 0x10002\n"                             \
-    "v_bitop3_b32 " TA ", " TA ", " TB ", s96 bitop3:0x68\n"      \
-    "s_and_b32 s97, " F ", 3\n"                                   \
-    "s_cbranch_scc0 " LBL "_%=\n"                                 \
-    "s_bfe_i32 s96, " F ", 0x10000\n"                             \
-    "s_bfe_i32 s97, " F ", 0x10001\n"                             \
-    "v_mov_b32 " TB ", s97\n"                                     \
-    "v_bitop3_b32 " TB ", " TA ", s96, " TB " bitop3:0xca\n"      \
-    "v_or_b32 %[m], %[m], " TB "\n"                               \
+// Gate: operands TA, TB with complement masks CA, CB and XOR mask XM; the result stays in TA.
+#define FES_RG_GATE(TA, TB, CA, CB, XM)          \
+    "v_xor_b32 " TA ", " CA ", " TA "\n"          \
+    "v_xor_b32 " TB ", " CB ", " TB "\n"          \
+    "v_bitop3_b32 " TA ", " TA ", " TB ", " XM " bitop3:0x68\n"
+// Output accumulation of one gate of a marked bundle (result TA, scratch TB, flags F).
+#define FES_RG_OUT(TA, TB, F, LBL)                                 \
+    "s_and_b32 s93, " F ", 3\n"                                     \
+    "s_cbranch_scc0 " LBL "_%=\n"                                   \
+    "s_bfe_i32 s92, " F ", 0x10000\n"                               \
+    "s_bfe_i32 s93, " F ", 0x10001\n"                               \
+    "v_mov_b32 " TB ", s93\n"                                       \
+    "v_bitop3_b32 " TB ", " TA ", s92, " TB " bitop3:0xca\n"        \
+    "v_or_b32 %[m], %[m], " TB "\n"                                 \
     LBL "_%=:\n"
-#define FES_RG_WRITES(X2, X6, X10, X14)                          \
-    "s_set_gpr_idx_on " X2 ", gpr_idx(DST)\n"                    \
-    "v_mov_b32 v24, v16\n"                                        \
-    "s_set_gpr_idx_idx " X6 "\n"                                  \
-    "v_mov_b32 v24, v18\n"                                        \
-    "s_set_gpr_idx_idx " X10 "\n"                                 \
-    "v_mov_b32 v24, v20\n"                                        \
-    "s_set_gpr_idx_idx " X14 "\n"                                 \
-    "v_mov_b32 v24, v22\n"                                        \
+#define FES_RG_WRITES(D0, D1, D2, D3)          \
+    "s_set_gpr_idx_on " D0 ", gpr_idx(DST)\n" \
+    "v_mov_b32 v24, v16\n"                     \
+    "s_set_gpr_idx_idx " D1 "\n"               \
+    "v_mov_b32 v24, v18\n"                     \
+    "s_set_gpr_idx_idx " D2 "\n"               \
+    "v_mov_b32 v24, v20\n"                     \
+    "s_set_gpr_idx_idx " D3 "\n"               \
+    "v_mov_b32 v24, v22\n"                     \
     "s_set_gpr_idx_off\n"
-#define FES_RG_BUFFER(b0, b1, b2, b3, b4, b5, b6, b7, b8, b9, b10, b11, b12, b13, b14, b15, P)             \
-    FES_RG_READS(b0, b1, b4, b5, b8, b9, b12, b13)                                                         \
-    FES_RG_GATE("v16", "v17", b0, b1, b3, "fes_rg" P "_g0")                                                \
-    FES_RG_GATE("v18", "v19", b4, b5, b7, "fes_rg" P "_g1")                                                \
-    FES_RG_GATE("v20", "v21", b8, b9, b11, "fes_rg" P "_g2")                                               \
-    FES_RG_GATE("v22", "v23", b12, b13, b15, "fes_rg" P "_g3")                                             \
-    FES_RG_WRITES(b2, b6, b10, b14)
-#define FES_RG_BUF_A                                                                                      \
-    FES_RG_BUFFER("s64", "s65", "s66", "s67", "s68", "s69", "s70", "s71", "s72", "s73", "s74", "s75", "s76", \
-                  "s77", "s78", "s79", "a")
-#define FES_RG_BUF_B                                                                                      \
-    FES_RG_BUFFER("s80", "s81", "s82", "s83", "s84", "s85", "s86", "s87", "s88", "s89", "s90", "s91", "s92", \
-                  "s93", "s94", "s95", "b")
+// One bundle from the 28 SGPRs of a buffer (words a0..a3, b0..b3, d0..d3, ca, cb, xm, fl).
+#define FES_RG_BUNDLE(a0, a1, a2, a3, b0, b1, b2, b3, d0, d1, d2, d3, ca0, ca1, ca2, ca3, cb0, cb1, cb2, cb3, x0, x1, \
+                      x2, x3, f0, f1, f2, f3, P)                                                                     \
+    FES_RG_READS(a0, b0, a1, b1, a2, b2, a3, b3)                                                                       \
+    FES_RG_GATE("v16", "v17", ca0, cb0, x0)                                                                            \
+    FES_RG_GATE("v18", "v19", ca1, cb1, x1)                                                                            \
+    FES_RG_GATE("v20", "v21", ca2, cb2, x2)                                                                            \
+    FES_RG_GATE("v22", "v23", ca3, cb3, x3)                                                                            \
+    "s_bitcmp1_b32 " d0 ", 31\n"                                                                                       \
+    "s_cbranch_scc0 fes_rg" P "_noout_%=\n"                                                                            \
+    FES_RG_OUT("v16", "v17", f0, "fes_rg" P "_o0") FES_RG_OUT("v18", "v19", f1, "fes_rg" P "_o1")                        \
+    FES_RG_OUT("v20", "v21", f2, "fes_rg" P "_o2") FES_RG_OUT("v22", "v23", f3, "fes_rg" P "_o3")                        \
+    "fes_rg" P "_noout_%=:\n"                                                                                          \
+    FES_RG_WRITES(d0, d1, d2, d3)
+// Buffer A: s36..s63, buffer B: s64..s91 (one bundle each, kRegsBundleWords = 28 words).
+#define FES_RG_BUF_A                                                                                         \
+    FES_RG_BUNDLE("s36", "s37", "s38", "s39", "s40", "s41", "s42", "s43", "s44", "s45", "s46", "s47", "s48", "s49", \
+                  "s50", "s51", "s52", "s53", "s54", "s55", "s56", "s57", "s58", "s59", "s60", "s61", "s62", "s63", \
+                  "a")
+#define FES_RG_BUF_B                                                                                         \
+    FES_RG_BUNDLE("s64", "s65", "s66", "s67", "s68", "s69", "s70", "s71", "s72", "s73", "s74", "s75", "s76", "s77", \
+                  "s78", "s79", "s80", "s81", "s82", "s83", "s84", "s85", "s86", "s87", "s88", "s89", "s90", "s91", \
+                  "b")
+#define FES_RG_LOAD(X16, X8, X4) \
+    "s_load_dwordx16 " X16 ", s[94:95], 0x0\n" \
+    "s_load_dwordx8 " X8 ", s[94:95], 0x40\n"  \
+    "s_load_dwordx4 " X4 ", s[94:95], 0x60\n"
 
 #define FES_RG_INPUT(I, ROW, VAL)            \
     "s_cmp_eq_u32 %[n], " #I "\n"            \
     "s_cbranch_scc1 fes_rg_in_done_%=\n"     \
     "v_mov_b32 " ROW ", " VAL "\n"
 
+// Registers: s92, s93 scratch; s[94:95] stream pointer; s96 bundles left; s97 input index;
+// s[98:99] a shifted copy of the pass index.
 #define FES_RG_PASS_ASM                                                                                   \
     "v_mov_b32 v24, 0\n"                                                                                  \
     FES_RG_INPUT(0, "v25", "0xaaaaaaaa") FES_RG_INPUT(1, "v26", "0xcccccccc")                              \
@@ -348,51 +366,53 @@ constexpr int kFileBase = 24;
     FES_RG_INPUT(10, "v35", "%[x10]")                                                                      \
     "s_cmp_eq_u32 %[n], 11\n"                                                                             \
     "s_cbranch_scc1 fes_rg_in_done_%=\n"                                                                  \
-    "s_mov_b32 s63, 11\n"                                                                                \
+    "s_mov_b32 s97, 11\n"                                                                                 \
     "fes_rg_in_loop_%=:\n"                                                                                \
-    "s_sub_u32 s62, s63, 5\n"                                                                           \
-    "s_lshr_b64 s[96:97], %[base], s62\n"                                                                \
-    "s_and_b32 s96, s96, 1\n"                                                                             \
-    "s_sub_u32 s96, 0, s96\n"                                                                             \
-    "s_add_u32 s97, s63, 1\n"                                                                            \
-    "s_set_gpr_idx_on s97, gpr_idx(DST)\n"                                                                \
-    "v_mov_b32 v24, s96\n"                                                                                \
+    "s_sub_u32 s96, s97, 5\n"                                                                             \
+    "s_lshr_b64 s[98:99], %[base], s96\n"                                                                 \
+    "s_and_b32 s98, s98, 1\n"                                                                             \
+    "s_sub_u32 s98, 0, s98\n"                                                                             \
+    "s_add_u32 s99, s97, 1\n"                                                                             \
+    "s_set_gpr_idx_on s99, gpr_idx(DST)\n"                                                                \
+    "v_mov_b32 v24, s98\n"                                                                                \
     "s_set_gpr_idx_off\n"                                                                                 \
-    "s_add_u32 s63, s63, 1\n"                                                                           \
-    "s_cmp_lt_u32 s63, %[n]\n"                                                                           \
+    "s_add_u32 s97, s97, 1\n"                                                                             \
+    "s_cmp_lt_u32 s97, %[n]\n"                                                                            \
     "s_cbranch_scc1 fes_rg_in_loop_%=\n"                                                                  \
     "fes_rg_in_done_%=:\n"                                                                                \
     "v_mov_b32 %[m], 0\n"                                                                                 \
-    "s_mov_b64 s[98:99], %[prog]\n"                                                                       \
-    "s_mov_b32 s62, %[nb]\n"                                                                             \
-    "s_load_dwordx16 s[64:79], s[98:99], 0x0\n"                                                           \
+    "s_mov_b64 s[94:95], %[prog]\n"                                                                       \
+    "s_mov_b32 s96, %[nb]\n"                                                                              \
+    FES_RG_LOAD("s[36:51]", "s[52:59]", "s[60:63]")                                                       \
     "fes_rg_loop_%=:\n"                                                                                   \
     "s_waitcnt lgkmcnt(0)\n"                                                                              \
-    "s_sub_u32 s62, s62, 1\n"                                                                           \
-    "s_cmp_eq_u32 s62, 0\n"                                                                              \
+    "s_sub_u32 s96, s96, 1\n"                                                                             \
+    "s_cmp_eq_u32 s96, 0\n"                                                                               \
     "s_cbranch_scc1 fes_rg_lasta_%=\n"                                                                    \
-    "s_add_u32 s98, s98, 64\n"                                                                            \
-    "s_addc_u32 s99, s99, 0\n"                                                                            \
-    "s_load_dwordx16 s[80:95], s[98:99], 0x0\n"                                                           \
+    "s_add_u32 s94, s94, 112\n"                                                                           \
+    "s_addc_u32 s95, s95, 0\n"                                                                            \
+    FES_RG_LOAD("s[64:79]", "s[80:87]", "s[88:91]")                                                       \
     "fes_rg_lasta_%=:\n"                                                                                  \
     FES_RG_BUF_A                                                                                          \
-    "s_cmp_eq_u32 s62, 0\n"                                                                              \
+    "s_cmp_eq_u32 s96, 0\n"                                                                               \
     "s_cbranch_scc1 fes_rg_end_%=\n"                                                                      \
     "s_waitcnt lgkmcnt(0)\n"                                                                              \
-    "s_sub_u32 s62, s62, 1\n"                                                                           \
-    "s_cmp_eq_u32 s62, 0\n"                                                                              \
+    "s_sub_u32 s96, s96, 1\n"                                                                             \
+    "s_cmp_eq_u32 s96, 0\n"                                                                               \
     "s_cbranch_scc1 fes_rg_lastb_%=\n"                                                                    \
-    "s_add_u32 s98, s98, 64\n"                                                                            \
-    "s_addc_u32 s99, s99, 0\n"                                                                            \
-    "s_load_dwordx16 s[64:79], s[98:99], 0x0\n"                                                           \
+    "s_add_u32 s94, s94, 112\n"                                                                           \
+    "s_addc_u32 s95, s95, 0\n"                                                                            \
+    FES_RG_LOAD("s[36:51]", "s[52:59]", "s[60:63]")                                                       \
     "fes_rg_lastb_%=:\n"                                                                                  \
     FES_RG_BUF_B                                                                                          \
-    "s_cmp_eq_u32 s62, 0\n"                                                                              \
+    "s_cmp_eq_u32 s96, 0\n"                                                                               \
     "s_cbranch_scc0 fes_rg_loop_%=\n"                                                                     \
     "fes_rg_end_%=:\n"
 
 #define FES_RG_SCLOB                                                                                      \
-    "m0", "scc", "s62", "s63", "s64", "s65", "s66", "s67", "s68", "s69", "s70", "s71", "s72", "s73", "s74", "s75", "s76",  \
+    "m0", "scc", "s36", "s37", "s38", "s39", "s40", "s41", "s42", "s43", "s44", "s45", "s46", "s47", "s48",  \
+        "s49", "s50", "s51", "s52", "s53", "s54", "s55", "s56", "s57", "s58", "s59", "s60", "s61", "s62",   \
+        "s63", "s64", "s65", "s66", "s67", "s68", "s69", "s70", "s71", "s72", "s73", "s74", "s75", "s76",   \
         "s77", "s78", "s79", "s80", "s81", "s82", "s83", "s84", "s85", "s86", "s87", "s88", "s89", "s90",   \
         "s91", "s92", "s93", "s94", "s95", "s96", "s97", "s98", "s99"
 #define FES_V10(d) "v" #d "0", "v" #d "1", "v" #d "2", "v" #d "3", "v" #d "4", "v" #d "5", "v" #d "6", \

@@ -74,6 +74,18 @@ hipError_t launch_interp_sim(const InterpLaunch& L, int K, int B, bool lds, int 
 hipError_t launch_signature_hash(const uint32_t* sig, uint64_t rows, uint64_t words, uint64_t* hash,
                                  uint64_t* ones, int grid, hipStream_t stream);
 
+// Register tier's stream: per bundle of 4 gates, 28 words in this order
+//   a[4]   operand rows with the complement flag in bit 31 (the kernel indexes registers by the
+//          low 8 bits, so the flag needs no masking),
+//   b[4]   the same for the second operands,
+//   d[4]   destination rows; bit 31 of d[0] is set when a gate of the bundle drives an output,
+//   ca[4], cb[4]  complement masks of the operands (0 or all ones),
+//   xm[4]  XOR masks (all ones for a fused three-AND XOR, else 0),
+//   fl[4]  the instruction flags (output polarity bits 0 and 1), read only in marked bundles.
+constexpr uint32_t kRegsBundleWords = 28;
+// Encode a bundled plan (bundle 4) into that layout.
+void encode_regs_stream(const Plan& p, std::vector<uint32_t>& out);
+
 // Register tier: value files in VGPRs (one wave per workgroup, bundles of 4, one 32-bit word per
 // lane).  interp_regs_rows: the file size (96, 136 or 232 rows) that holds `rows`, 0 if none
 // does, with the waves per SIMD it allows.  launch_interp_regs: `regs` is that file size.

@@ -59,11 +59,13 @@ uint64_t noalloc_check(Device& dev, Circuit& c, const fastlec_es_options& o, con
     std::vector<Circuit*> one{&c};
     const Schedule sch = default_schedule(dev, one, &o);
     const Plan& p = c.plan_for((uint32_t)sch.B);
-    const size_t prog_bytes = p.prog.size() * sizeof(Instr);
+    // the register tier runs its own encoding of the stream, the other tiers the plan's
+    const void* prog_src = sch.regs ? (const void*)c.regs_stream().data() : (const void*)p.prog.data();
+    const size_t prog_bytes = sch.regs ? c.regs_stream().size() * sizeof(uint32_t) : p.prog.size() * sizeof(Instr);
     if (kProgOff + prog_bytes > kScratchBytes)
-        throw Error{kErrInvalid, "instruction stream of " + std::to_string(p.prog.size()) +
-                                     " instructions exceeds the no-allocation scratch (at most " +
-                                     std::to_string((kScratchBytes - kProgOff) / sizeof(Instr)) + ")"};
+        throw Error{kErrInvalid, "instruction stream of " + std::to_string(p.prog.size()) + " instructions (" +
+                                     std::to_string(prog_bytes) + " bytes) exceeds the no-allocation scratch (" +
+                                     std::to_string(kScratchBytes - kProgOff) + " bytes)"};
     if (!sch.lds && !sch.regs)
         throw Error{kErrInvalid, "value file does not fit in LDS with this schedule; the no-allocation entry point "
                                  "has no device-memory value files"};
@@ -93,7 +95,7 @@ uint64_t noalloc_check(Device& dev, Circuit& c, const fastlec_es_options& o, con
     const auto t0 = std::chrono::steady_clock::now();
     FES_HIP(hipMemcpyAsync(base, head.bytes, sizeof(head.bytes), hipMemcpyHostToDevice, stream));
     if (prog_bytes)
-        FES_HIP(hipMemcpyAsync(base + kProgOff, p.prog.data(), prog_bytes, hipMemcpyHostToDevice, stream));
+        FES_HIP(hipMemcpyAsync(base + kProgOff, prog_src, prog_bytes, hipMemcpyHostToDevice, stream));
     FES_HIP(launch_schedule(L, s, stream));
     FES_HIP(hipMemcpyAsync(&best, base + kBestOff, 8, hipMemcpyDeviceToHost, stream));
     FES_HIP(hipStreamSynchronize(stream));

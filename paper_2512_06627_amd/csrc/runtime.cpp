@@ -49,6 +49,14 @@ Circuit::~Circuit() {
             (void)hipSetDevice(cur);
         }
     }
+    for (auto& kv : dev_regs) {
+        if (!kv.second) continue;
+        int cur = 0;
+        if (hipGetDevice(&cur) == hipSuccess && hipSetDevice(kv.first) == hipSuccess) {
+            (void)hipFree(kv.second);
+            (void)hipSetDevice(cur);
+        }
+    }
     for (auto& kv : dev_prog) {
         if (!kv.second) continue;
         int cur = 0;
@@ -92,6 +100,49 @@ const Instr* Circuit::device_prog(int dev, uint32_t bundle, hipStream_t s) {
         FES_HIP(hipStreamSynchronize(s));
     }
     dev_prog[key] = d;
+    return d;
+}
+
+void encode_regs_stream(const Plan& p, std::vector<uint32_t>& out) {
+    if (p.bundle != 4 || p.prog.size() % 4) throw Error{kErrInvalid, "register-tier stream needs bundles of 4"};
+    out.assign(p.prog.size() / 4 * kRegsBundleWords, 0u);
+    for (size_t b = 0; b < p.prog.size() / 4; ++b) {
+        uint32_t* w = out.data() + b * kRegsBundleWords;
+        bool any_out = false;
+        for (int u = 0; u < 4; ++u) {
+            const Instr& ins = p.prog[b * 4 + u];
+            w[u] = ins.a;
+            w[4 + u] = ins.b;
+            w[8 + u] = ins.d;
+            w[12 + u] = (ins.a & kCompl) ? ~0u : 0u;
+            w[16 + u] = (ins.b & kCompl) ? ~0u : 0u;
+            w[20 + u] = (ins.flags & kXor) ? ~0u : 0u;
+            w[24 + u] = ins.flags & (kOutPos | kOutNeg);
+            any_out = any_out || (ins.flags & (kOutPos | kOutNeg));
+        }
+        if (any_out) w[8] |= 0x80000000u;
+    }
+}
+
+const std::vector<uint32_t>& Circuit::regs_stream() {
+    const Plan& p = plan_for(4);
+    std::lock_guard<std::mutex> g(mu);
+    if (regs_host.empty() && !p.prog.empty()) encode_regs_stream(p, regs_host);
+    return regs_host;
+}
+
+const uint32_t* Circuit::device_regs_stream(int dev, hipStream_t s) {
+    const std::vector<uint32_t>& h = regs_stream();
+    std::lock_guard<std::mutex> g(mu);
+    auto it = dev_regs.find(dev);
+    if (it != dev_regs.end()) return it->second;
+    uint32_t* d = nullptr;
+    FES_HIP(hipMalloc(&d, std::max<size_t>(h.size(), 1) * sizeof(uint32_t)));
+    if (!h.empty()) {
+        FES_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+        FES_HIP(hipStreamSynchronize(s));
+    }
+    dev_regs[dev] = d;
     return d;
 }
 
@@ -356,8 +407,9 @@ uint64_t build_descs(Device& dev, const std::vector<Circuit*>& cs, const std::ve
     for (size_t t = 0; t < k; ++t) {
         size_t i = order[t];
         Circuit* c = cs[i];
-        item = fill_desc(c->plan_for(sch.B), c->device_prog(dev.ordinal, sch.B, stream), ranges[i], best_index[i],
-                         sch, item, out[t]);
+        const Instr* prog = sch.regs ? (const Instr*)c->device_regs_stream(dev.ordinal, stream)
+                                     : c->device_prog(dev.ordinal, sch.B, stream);
+        item = fill_desc(c->plan_for(sch.B), prog, ranges[i], best_index[i], sch, item, out[t]);
     }
     return item;
 }

@@ -90,6 +90,13 @@ struct Circuit {
     const LutProgram& lut_program();
     // Value-file rows of the interpreter's stream in bundles of 4 (the runtime model's tier).
     uint32_t interp_rows() { return plan_for(4).rows; }
+    // The register tier's stream: the plan in bundles of 4, each bundle kRegsBundleWords words
+    // (operand and destination words, complement and XOR masks, output flags; see
+    // encode_regs_stream).  Host copy and per-device copies, built on first use.
+    const std::vector<uint32_t>& regs_stream();
+    const uint32_t* device_regs_stream(int device, hipStream_t s);
+    std::vector<uint32_t> regs_host;
+    std::map<int, uint32_t*> dev_regs;
     // LUT steps of the specialized program if it is built, else the model's estimate (never
     // builds it).
     uint32_t lut_steps_known();
