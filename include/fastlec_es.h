@@ -159,10 +159,10 @@ int fastlec_es_check_batch(const fastlec_es_circuit *const *cs, size_t k, const 
 
 /* For callers that cannot allocate device memory (code that must not call hipMalloc, such as
  * work recorded under HIP graph capture, tight serving loops, harnesses that forbid it): the
- * same check as fastlec_es_check with the interpreter kernel and value files in LDS, whose
- * control block, best value, descriptor and a copy of the circuit's instruction stream live
- * in a static device array of FASTLEC_NOALLOC_SCRATCH_BYTES bytes instead of library
- * allocations.  It calls no hipMalloc, hipFree, hipHostMalloc or event creation; it copies
+ * same check as fastlec_es_check with the interpreter kernel and value files in registers or
+ * LDS, whose control block, best value, descriptor and a copy of the circuit's instruction
+ * stream live in a static device array of FASTLEC_NOALLOC_SCRATCH_BYTES bytes instead of
+ * library allocations.  It calls no hipMalloc, hipFree, hipHostMalloc or event creation; it copies
  * from pageable host memory and waits on the stream.  The first library call on a device
  * (any entry point) sets the device up (properties, library streams, the array's address);
  * make that call outside any code that must not allocate.
@@ -171,7 +171,8 @@ int fastlec_es_check_batch(const fastlec_es_circuit *const *cs, size_t k, const 
  * Same answer fields as fastlec_es_check; kernel_ms is the host time from the first upload to
  * the end of the wait (no HIP events are created).
  * Errors: FASTLEC_ERR_INVALID when the bundled instruction stream does not fit the array
- * (about 65,000 instructions), when the circuit's value file does not fit in LDS, or for the
+ * (about 37,000 instructions at 28 bytes each when the value file fits in registers, about
+ * 65,000 at 16 bytes in LDS), when the circuit's value file fits in neither, or for the
  * options above.  The array keeps the last call's contents; every call uploads all of it that
  * it reads.  Calls on one device share the array: the library lets one run at a time per
  * device (a host lock held until the call's results are on the host); calls that overlap on
@@ -313,7 +314,7 @@ int fastlec_es_submiter_aag(const fastlec_es_circuit *c, const uint32_t *class_o
  *                   (num_instrs - 2 * num_xors); R depends on the value-file size (S)
  *   specialized_ms  t0 + (LUT steps) * max(1, patterns / 2048) / R
  *   compile_ms      hipRTC compile of the specialized kernel: c0 + c1 * (LUT steps)
- * Median errors on the fitting set: 3%, 17%, 6%.  Outputs may be NULL; asking for
+ * Median errors on the fitting set: 6%, 16%, 2%.  Outputs may be NULL; asking for
  * specialized_ms or compile_ms builds the circuit's LUT program (host time).  The AUTO kernel
  * choice of fastlec_es_check uses the same model. */
 int fastlec_es_predict(const fastlec_es_circuit *c, uint64_t begin_word, uint64_t end_word, double *interp_ms,

@@ -236,7 +236,7 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
         // Cones the runtime model gives to the specialized kernel (AUTO only) run as their own
         // launches; the rest share interpreter launches.  Their kernels compile together as
         // few hipRTC programs, so a cone is a candidate when its predicted saving beats its
-        // own share of the compile (margin 1.5 on the per-LUT part), and the candidates are
+        // own share of the compile (kCompileMargin on the per-LUT part), and the candidates are
         // taken when their summed saving also covers one program's fixed cost (same margin).
         std::vector<size_t> spec;
         std::vector<uint8_t> is_spec(k, 0);
@@ -322,15 +322,22 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
         // so cones with few rows would otherwise run at the occupancy of the largest.  Rows
         // are bucketed by powers of two; each group gets its own schedule and recorded launch,
         // and the groups run back to back on the stream.
+        // Cones whose files fit the register tier are grouped by its file size (96, 136, 232
+        // rows: the waves per SIMD a launch gets), the others by powers of two of their rows.
         std::map<uint32_t, std::vector<size_t>> groups;
         for (size_t i = 0; i < k; ++i) {
             if (is_spec[i] || is_alone[i]) continue;
+            const int t = regs_tier_enabled() ? model_interp_tier(v[i]->interp_rows()) : 3;
+            if (t < 3) {
+                groups[(uint32_t)t].push_back(i);
+                continue;
+            }
             uint32_t rows = v[i]->plan_for(8).rows, b = 0;
             while (rows > 1) {
                 rows >>= 1;
                 ++b;
             }
-            groups[b].push_back(i);
+            groups[3 + b].push_back(i);
         }
         double total_ms = 0;
         for (auto& gi : groups) {

@@ -4,20 +4,20 @@
 
 namespace fes {
 
-// Fitted on one MI355X by least squares on relative error (plain checks of 37 seeded cones and the
-// multiplier and MAC miters, n 12..32; paper_2512_06627_amd/calibrate.py): median (largest)
-// relative error 3% (15%) interpreter, 17% (60%) specialized, 6% (12%) compile.  Interpreter gates are
+// Fitted on one MI355X by least squares on relative error (plain checks of 33 seeded layered cones
+// and four multiplier and MAC miters, n 12..32; paper_2512_06627_amd/calibrate.py): median (largest)
+// relative error 6% (32%) interpreter, 16% (60%) specialized, 2% (4%) compile.  Interpreter gates are
 // the instructions of its bundled stream (three-AND XORs count once); its rate depends on the tier
 // that holds the value file.
 namespace model {
-constexpr double kInterpT0Ms = 0.0140;
+constexpr double kInterpT0Ms = 0.0120;
 constexpr uint32_t kTierRows[3] = {96, 136, 232};  // register tier files; LDS or device memory above
-constexpr double kInterpRate[4] = {1.092e14, 1.135e14, 9.48e13, 2.18e13};  // gate instructions*patterns/s
-constexpr double kInterpMsPerGateFloor = 3.98e-5; // one wave pass per gate: spaces below a chip's waves
+constexpr double kInterpRate[4] = {1.345e14, 1.402e14, 1.260e14, 2.17e13};  // gate instructions*patterns/s
+constexpr double kInterpMsPerGateFloor = 3.16e-5; // one wave pass per gate: spaces below a chip's waves
 constexpr double kSpecT0Ms = 0.0135;
-constexpr double kSpecLutPassesPerS = 6.36e11;
-constexpr double kCompileC0Ms = 118.4;
-constexpr double kCompileMsPerLut = 0.00685;
+constexpr double kSpecLutPassesPerS = 6.29e11;
+constexpr double kCompileC0Ms = 108.5;
+constexpr double kCompileMsPerLut = 0.00667;
 constexpr double kLutsPerGate = 0.30;
 }  // namespace model
 
