@@ -366,7 +366,10 @@ size_t fastlec_es_specialized_source(const fastlec_es_circuit *c, int waves_per_
 /* Replay the interpreter instruction stream planned with `bundle` (1, 4, 8 or 16) on the host,
  * with the kernels' bundle semantics, for the 32-pattern half-words hw .. hw+count-1
  * (half-word h holds patterns 32h .. 32h+31, bit j = pattern 32h+j).  out: count host
- * words of miter values.  Checks the plan's slot map first (FASTLEC_ERR_INVALID if broken). */
+ * words of miter values.  Checks the plan's slot map first (FASTLEC_ERR_INVALID if broken).
+ * bundle 0 replays the register tier's encoded stream (bundles of 4 with precomputed masks,
+ * rows taken from the low 8 bits of each word, outputs only in marked bundles), as that
+ * kernel reads it; FASTLEC_ERR_INVALID when the value file does not fit that tier. */
 int fastlec_es_host_replay(const fastlec_es_circuit *c, uint32_t bundle, uint64_t hw, uint64_t count,
                            uint32_t *out);
 

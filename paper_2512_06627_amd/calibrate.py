@@ -9,7 +9,7 @@ fixed launch cost:
 
 * interpreter: t = t0 + N * max(2^n / R, L), N = gate instructions of its stream (AND gates
   of the cone, each fused three-AND XOR counted once), with one rate R per value-file tier
-  (register tier files of at most 96, 136 and 232 rows, at four, three and two waves per SIMD;
+  (register tier files of at most 104, 144 and 232 rows, at four, three and two waves per SIMD;
   LDS or device memory above: the interpreter's rate follows the waves a SIMD holds); L is the
   time per gate of one wave's pass, the floor when the space has fewer passes than the chip has
   waves;
@@ -80,7 +80,7 @@ def fit_linear(x, t):
     return float(a), float(b), float(np.median(np.abs(rel))), float(np.max(np.abs(rel)))
 
 
-TIER_ROWS = (96, 136, 232)  # register tier files; LDS or device memory above
+TIER_ROWS = (104, 144, 232)  # register tier files; LDS or device memory above
 
 
 def tier(rows):

@@ -322,7 +322,7 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
         // so cones with few rows would otherwise run at the occupancy of the largest.  Rows
         // are bucketed by powers of two; each group gets its own schedule and recorded launch,
         // and the groups run back to back on the stream.
-        // Cones whose files fit the register tier are grouped by its file size (96, 136, 232
+        // Cones whose files fit the register tier are grouped by its file size (104, 144, 232
         // rows: the waves per SIMD a launch gets), the others by powers of two of their rows.
         std::map<uint32_t, std::vector<size_t>> groups;
         for (size_t i = 0; i < k; ++i) {
@@ -460,13 +460,55 @@ int fastlec_es_host_replay_specialized(const fastlec_es_circuit* c, uint64_t hw,
     });
 }
 
+// Replay of the register tier's encoded stream with that kernel's reading of it: row numbers
+// are the low 8 bits of the operand and destination words, the complement and XOR masks are
+// the stream's own words, and outputs count only in bundles whose mark bit is set.
+void replay_regs_stream(Circuit& cc, uint64_t hw, uint64_t count, uint32_t* out) {
+    const Plan& p = cc.plan_for(4);
+    int waves = 0;
+    if (!interp_regs_rows(p.rows, &waves)) throw Error{kErrInvalid, "value file does not fit the register tier"};
+    const std::vector<uint32_t>& rs = cc.regs_stream();
+    const size_t nb = p.prog.size() / 4;
+    if (rs.size() != (nb + 1) * kRegsBundleWords) throw Error{kErrInvalid, "register stream size"};
+    for (size_t k = nb * kRegsBundleWords; k < rs.size(); ++k)
+        if (rs[k]) throw Error{kErrInvalid, "register stream padding is not zero"};
+    static const uint32_t kc[5] = {0xAAAAAAAAu, 0xCCCCCCCCu, 0xF0F0F0F0u, 0xFF00FF00u, 0xFFFF0000u};
+    std::vector<uint32_t> rows(256, 0);
+    for (uint64_t t = 0; t < count; ++t) {
+        const uint64_t h = hw + t;
+        rows[0] = 0;
+        for (uint32_t i = 0; i < p.num_inputs; ++i) rows[1 + i] = i < 5 ? kc[i] : 0u - (uint32_t)((h >> (i - 5)) & 1u);
+        uint32_t m = 0;
+        for (size_t b = 0; b < nb; ++b) {
+            const uint32_t* w = rs.data() + b * kRegsBundleWords;
+            uint32_t val[4];
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t x = rows[w[u] & 0xFFu] ^ w[12 + u], y = rows[w[4 + u] & 0xFFu] ^ w[16 + u];
+                val[u] = (w[20 + u] & (x ^ y)) | (~w[20 + u] & x & y);
+            }
+            const bool marked = (w[8] >> 31) != 0;
+            for (int u = 0; u < 4; ++u) {
+                rows[w[8 + u] & 0xFFu] = val[u];
+                if (marked && (w[24 + u] & kOutPos)) m |= val[u];
+                if (marked && (w[24 + u] & kOutNeg)) m |= ~val[u];
+            }
+        }
+        out[t] = m;
+    }
+}
+
 // Replay of the interpreter instruction stream on the host (bundle semantics: all reads of a
 // bundle, then all writes), for validating plans without a GPU.  Returns the miter words of
-// the 32-pattern half-words [hw, hw + count) in out.
+// the 32-pattern half-words [hw, hw + count) in out.  Bundle 0 replays the register tier's
+// encoded stream instead.
 int fastlec_es_host_replay(const fastlec_es_circuit* c, uint32_t bundle, uint64_t hw, uint64_t count, uint32_t* out) {
     return guarded([&] {
         if (!c || !out) throw Error{kErrInvalid, "null argument"};
         Circuit& cc = const_cast<Circuit&>(c->c);
+        if (bundle == 0) {
+            replay_regs_stream(cc, hw, count, out);
+            return FASTLEC_OK;
+        }
         const Plan& p = cc.plan_for(bundle);
         std::string err = validate_plan(bundle <= 1 ? cc.aig : cc.fused, p);
         if (!err.empty()) throw Error{kErrInvalid, "invalid plan: " + err};

@@ -266,9 +266,10 @@ hipError_t launch_k(const InterpLaunch& L, int B, bool lds, int grid, int block,
 // operand and destination words themselves: only their low 8 bits count, so a row with its
 // complement flag (or the bundle's output mark) in bit 31 indexes the right register.  Bundles
 // of four gates keep the stream's read-all-then-write-all semantics: the eight operands go to
-// v16..v23, the four results are computed and written back.  The stream is the register tier's
-// own encoding (encode_regs_stream: complement and XOR masks precomputed, one output mark per
-// bundle), so a gate costs no scalar instruction besides its three index moves.  It comes in by
+// v16..v23, complemented by the instruction that reads them, then each result is selected and
+// written to its row by one instruction.  The stream is the register tier's own encoding
+// (encode_regs_stream: complement and XOR masks precomputed, one output mark per bundle), so a
+// gate costs three VALU instructions and three index moves.  It comes in by
 // scalar loads, one bundle (112 bytes) ahead into a second set of SGPRs; with no LDS operations
 // in the pass, the scalar wait counter tracks only those loads.
 //
@@ -278,30 +279,42 @@ hipError_t launch_k(const InterpLaunch& L, int B, bool lds, int grid, int block,
 // miter word.
 constexpr int kFileBase = 24;
 
-// Eight operand reads of a bundle (a0, b0, ..., a3, b3 into v16..v23) through the SRC0 index.
-#define FES_RG_READS(A0, B0, A1, B1, A2, B2, A3, B3) \
-    "s_set_gpr_idx_on " A0 ", gpr_idx(SRC0)\n"       \
-    "v_mov_b32 v16, v24\n"                            \
-    "s_set_gpr_idx_idx " B0 "\n"                      \
-    "v_mov_b32 v17, v24\n"                            \
-    "s_set_gpr_idx_idx " A1 "\n"                      \
-    "v_mov_b32 v18, v24\n"                            \
-    "s_set_gpr_idx_idx " B1 "\n"                      \
-    "v_mov_b32 v19, v24\n"                            \
-    "s_set_gpr_idx_idx " A2 "\n"                      \
-    "v_mov_b32 v20, v24\n"                            \
-    "s_set_gpr_idx_idx " B2 "\n"                      \
-    "v_mov_b32 v21, v24\n"                            \
-    "s_set_gpr_idx_idx " A3 "\n"                      \
-    "v_mov_b32 v22, v24\n"                            \
-    "s_set_gpr_idx_idx " B3 "\n"                      \
-    "v_mov_b32 v23, v24\n"                            \
-    "s_set_gpr_idx_off\n"
-// Gate: operands TA, TB with complement masks CA, CB and XOR mask XM; the result stays in TA.
-#define FES_RG_GATE(TA, TB, CA, CB, XM)          \
-    "v_xor_b32 " TA ", " CA ", " TA "\n"          \
-    "v_xor_b32 " TB ", " CB ", " TB "\n"          \
-    "v_bitop3_b32 " TA ", " TA ", " TB ", " XM " bitop3:0x68\n"
+// Eight operand reads of a bundle through the SRC0 index, each with its complement mask applied
+// by the reading instruction itself: v16 = a0 ^ ca0, v17 = b0 ^ cb0, ..., v23 = b3 ^ cb3.  Index
+// mode is left on (SRC0): the next s_set_gpr_idx_on replaces index and mode, and code that
+// runs other VALU instructions first switches it off.
+#define FES_RG_READS(A0, B0, A1, B1, A2, B2, A3, B3, CA0, CB0, CA1, CB1, CA2, CB2, CA3, CB3) \
+    "s_set_gpr_idx_on " A0 ", gpr_idx(SRC0)\n"                                                \
+    "v_xor_b32_e64 v16, v24, " CA0 "\n"                                                        \
+    "s_set_gpr_idx_idx " B0 "\n"                                                               \
+    "v_xor_b32_e64 v17, v24, " CB0 "\n"                                                        \
+    "s_set_gpr_idx_idx " A1 "\n"                                                               \
+    "v_xor_b32_e64 v18, v24, " CA1 "\n"                                                        \
+    "s_set_gpr_idx_idx " B1 "\n"                                                               \
+    "v_xor_b32_e64 v19, v24, " CB1 "\n"                                                        \
+    "s_set_gpr_idx_idx " A2 "\n"                                                               \
+    "v_xor_b32_e64 v20, v24, " CA2 "\n"                                                        \
+    "s_set_gpr_idx_idx " B2 "\n"                                                               \
+    "v_xor_b32_e64 v21, v24, " CB2 "\n"                                                        \
+    "s_set_gpr_idx_idx " A3 "\n"                                                               \
+    "v_xor_b32_e64 v22, v24, " CA3 "\n"                                                        \
+    "s_set_gpr_idx_idx " B3 "\n"                                                               \
+    "v_xor_b32_e64 v23, v24, " CB3 "\n"
+// The gate's select over (XOR mask, a, b): a ^ b where the mask is set, a & b elsewhere (table
+// 0x68), written straight into the destination row through the DST index.  The mask is an SGPR,
+// so no source of the select is a VGPR the index applies to.  Index mode is left on (DST): only
+// scalar instructions follow until the next bundle's reads (the pass switches it off at its end).
+#define FES_RG_COMPUTE_WRITES(D0, D1, D2, D3, X0, X1, X2, X3)          \
+    "s_set_gpr_idx_on " D0 ", gpr_idx(DST)\n"                         \
+    "v_bitop3_b32 v24, " X0 ", v16, v17 bitop3:0x68\n"                 \
+    "s_set_gpr_idx_idx " D1 "\n"                                       \
+    "v_bitop3_b32 v24, " X1 ", v18, v19 bitop3:0x68\n"                 \
+    "s_set_gpr_idx_idx " D2 "\n"                                       \
+    "v_bitop3_b32 v24, " X2 ", v20, v21 bitop3:0x68\n"                 \
+    "s_set_gpr_idx_idx " D3 "\n"                                       \
+    "v_bitop3_b32 v24, " X3 ", v22, v23 bitop3:0x68\n"
+// Bundles that hold an output: the select into TA first, then the output test, then the write.
+#define FES_RG_GATE(TA, TB, XM) "v_bitop3_b32 " TA ", " XM ", " TA ", " TB " bitop3:0x68\n"
 // Output accumulation of one gate of a marked bundle (result TA, scratch TB, flags F).
 #define FES_RG_OUT(TA, TB, F, LBL)                                 \
     "s_and_b32 s93, " F ", 3\n"                                     \
@@ -322,41 +335,57 @@ constexpr int kFileBase = 24;
     "s_set_gpr_idx_idx " D3 "\n"               \
     "v_mov_b32 v24, v22\n"                     \
     "s_set_gpr_idx_off\n"
-// One bundle from the 28 SGPRs of a buffer (words a0..a3, b0..b3, d0..d3, ca, cb, xm, fl).
+// One bundle from the 28 SGPRs of a buffer (words a0..a3, b0..b3, d0..d3, ca, cb, xm, fl).  A
+// bundle with its output mark (bit 31 of d0) branches to its out-of-line copy (FES_RG_MARKED),
+// which returns to the label after it.
 #define FES_RG_BUNDLE(a0, a1, a2, a3, b0, b1, b2, b3, d0, d1, d2, d3, ca0, ca1, ca2, ca3, cb0, cb1, cb2, cb3, x0, x1, \
                       x2, x3, f0, f1, f2, f3, P)                                                                     \
-    FES_RG_READS(a0, b0, a1, b1, a2, b2, a3, b3)                                                                       \
-    FES_RG_GATE("v16", "v17", ca0, cb0, x0)                                                                            \
-    FES_RG_GATE("v18", "v19", ca1, cb1, x1)                                                                            \
-    FES_RG_GATE("v20", "v21", ca2, cb2, x2)                                                                            \
-    FES_RG_GATE("v22", "v23", ca3, cb3, x3)                                                                            \
+    FES_RG_READS(a0, b0, a1, b1, a2, b2, a3, b3, ca0, cb0, ca1, cb1, ca2, cb2, ca3, cb3)                               \
     "s_bitcmp1_b32 " d0 ", 31\n"                                                                                       \
-    "s_cbranch_scc0 fes_rg" P "_noout_%=\n"                                                                            \
+    "s_cbranch_scc1 fes_rg" P "_marked_%=\n"                                                                           \
+    FES_RG_COMPUTE_WRITES(d0, d1, d2, d3, x0, x1, x2, x3)                                                              \
+    "fes_rg" P "_back_%=:\n"
+#define FES_RG_MARKED(a0, a1, a2, a3, b0, b1, b2, b3, d0, d1, d2, d3, ca0, ca1, ca2, ca3, cb0, cb1, cb2, cb3, x0, x1, \
+                      x2, x3, f0, f1, f2, f3, P)                                                                     \
+    "fes_rg" P "_marked_%=:\n"                                                                                         \
+    "s_set_gpr_idx_off\n"                                                                                              \
+    FES_RG_GATE("v16", "v17", x0) FES_RG_GATE("v18", "v19", x1) FES_RG_GATE("v20", "v21", x2)                          \
+    FES_RG_GATE("v22", "v23", x3)                                                                                      \
     FES_RG_OUT("v16", "v17", f0, "fes_rg" P "_o0") FES_RG_OUT("v18", "v19", f1, "fes_rg" P "_o1")                        \
     FES_RG_OUT("v20", "v21", f2, "fes_rg" P "_o2") FES_RG_OUT("v22", "v23", f3, "fes_rg" P "_o3")                        \
-    "fes_rg" P "_noout_%=:\n"                                                                                          \
-    FES_RG_WRITES(d0, d1, d2, d3)
+    FES_RG_WRITES(d0, d1, d2, d3)                                                                                      \
+    "s_branch fes_rg" P "_back_%=\n"
 // Buffer A: s36..s63, buffer B: s64..s91 (one bundle each, kRegsBundleWords = 28 words).
-#define FES_RG_BUF_A                                                                                         \
-    FES_RG_BUNDLE("s36", "s37", "s38", "s39", "s40", "s41", "s42", "s43", "s44", "s45", "s46", "s47", "s48", "s49", \
-                  "s50", "s51", "s52", "s53", "s54", "s55", "s56", "s57", "s58", "s59", "s60", "s61", "s62", "s63", \
-                  "a")
-#define FES_RG_BUF_B                                                                                         \
-    FES_RG_BUNDLE("s64", "s65", "s66", "s67", "s68", "s69", "s70", "s71", "s72", "s73", "s74", "s75", "s76", "s77", \
-                  "s78", "s79", "s80", "s81", "s82", "s83", "s84", "s85", "s86", "s87", "s88", "s89", "s90", "s91", \
-                  "b")
-#define FES_RG_LOAD(X16, X8, X4) \
-    "s_load_dwordx16 " X16 ", s[94:95], 0x0\n" \
-    "s_load_dwordx8 " X8 ", s[94:95], 0x40\n"  \
-    "s_load_dwordx4 " X4 ", s[94:95], 0x60\n"
+#define FES_RG_REGS_A(M)                                                                                    \
+    M("s36", "s37", "s38", "s39", "s40", "s41", "s42", "s43", "s44", "s45", "s46", "s47", "s48", "s49", "s50", \
+      "s51", "s52", "s53", "s54", "s55", "s56", "s57", "s58", "s59", "s60", "s61", "s62", "s63", "a")
+#define FES_RG_REGS_B(M)                                                                                    \
+    M("s64", "s65", "s66", "s67", "s68", "s69", "s70", "s71", "s72", "s73", "s74", "s75", "s76", "s77", "s78", \
+      "s79", "s80", "s81", "s82", "s83", "s84", "s85", "s86", "s87", "s88", "s89", "s90", "s91", "b")
+#define FES_RG_BUF_A FES_RG_REGS_A(FES_RG_BUNDLE)
+#define FES_RG_BUF_B FES_RG_REGS_B(FES_RG_BUNDLE)
+// Bundle k of the pair at s[94:95] (k = 0, 1 or 2: 112-byte bundles) into buffer A or B.
+#define FES_RG_LOAD_A(O16, O8, O4)                  \
+    "s_load_dwordx16 s[36:51], s[94:95], " O16 "\n" \
+    "s_load_dwordx8 s[52:59], s[94:95], " O8 "\n"   \
+    "s_load_dwordx4 s[60:63], s[94:95], " O4 "\n"
+#define FES_RG_LOAD_B(O16, O8, O4)                  \
+    "s_load_dwordx16 s[64:79], s[94:95], " O16 "\n" \
+    "s_load_dwordx8 s[80:87], s[94:95], " O8 "\n"   \
+    "s_load_dwordx4 s[88:91], s[94:95], " O4 "\n"
 
 #define FES_RG_INPUT(I, ROW, VAL)            \
     "s_cmp_eq_u32 %[n], " #I "\n"            \
     "s_cbranch_scc1 fes_rg_in_done_%=\n"     \
     "v_mov_b32 " ROW ", " VAL "\n"
 
-// Registers: s92, s93 scratch; s[94:95] stream pointer; s96 bundles left; s97 input index;
-// s[98:99] a shifted copy of the pass index.
+// Registers: s92, s93 scratch; s[94:95] stream pointer (advanced by two bundles per loop
+// iteration: buffer A runs the bundle at the pointer, B the next); s96 bundles left after the
+// current one (the loop ends when subtracting one borrows); s97 input index; s[98:99] a shifted
+// copy of the pass index.  Every bundle's successor is loaded while it runs, so the last one
+// loads the stream's padding bundle; the pass waits for that load before it ends, since the
+// compiler takes the clobbered SGPRs as free once the statement is over (a load still in flight
+// then overwrote the compiler's own values: correct answers, tens of times slower).
 #define FES_RG_PASS_ASM                                                                                   \
     "v_mov_b32 v24, 0\n"                                                                                  \
     FES_RG_INPUT(0, "v25", "0xaaaaaaaa") FES_RG_INPUT(1, "v26", "0xcccccccc")                              \
@@ -382,32 +411,27 @@ constexpr int kFileBase = 24;
     "fes_rg_in_done_%=:\n"                                                                                \
     "v_mov_b32 %[m], 0\n"                                                                                 \
     "s_mov_b64 s[94:95], %[prog]\n"                                                                       \
-    "s_mov_b32 s96, %[nb]\n"                                                                              \
-    FES_RG_LOAD("s[36:51]", "s[52:59]", "s[60:63]")                                                       \
+    "s_sub_u32 s96, %[nb], 1\n"                                                                           \
+    FES_RG_LOAD_A("0x0", "0x40", "0x60")                                                                  \
     "fes_rg_loop_%=:\n"                                                                                   \
     "s_waitcnt lgkmcnt(0)\n"                                                                              \
-    "s_sub_u32 s96, s96, 1\n"                                                                             \
-    "s_cmp_eq_u32 s96, 0\n"                                                                               \
-    "s_cbranch_scc1 fes_rg_lasta_%=\n"                                                                    \
-    "s_add_u32 s94, s94, 112\n"                                                                           \
-    "s_addc_u32 s95, s95, 0\n"                                                                            \
-    FES_RG_LOAD("s[64:79]", "s[80:87]", "s[88:91]")                                                       \
-    "fes_rg_lasta_%=:\n"                                                                                  \
+    FES_RG_LOAD_B("0x70", "0xb0", "0xd0")                                                                 \
     FES_RG_BUF_A                                                                                          \
-    "s_cmp_eq_u32 s96, 0\n"                                                                               \
+    "s_sub_u32 s96, s96, 1\n"                                                                             \
     "s_cbranch_scc1 fes_rg_end_%=\n"                                                                      \
     "s_waitcnt lgkmcnt(0)\n"                                                                              \
-    "s_sub_u32 s96, s96, 1\n"                                                                             \
-    "s_cmp_eq_u32 s96, 0\n"                                                                               \
-    "s_cbranch_scc1 fes_rg_lastb_%=\n"                                                                    \
-    "s_add_u32 s94, s94, 112\n"                                                                           \
-    "s_addc_u32 s95, s95, 0\n"                                                                            \
-    FES_RG_LOAD("s[36:51]", "s[52:59]", "s[60:63]")                                                       \
-    "fes_rg_lastb_%=:\n"                                                                                  \
+    FES_RG_LOAD_A("0xe0", "0x120", "0x140")                                                               \
     FES_RG_BUF_B                                                                                          \
-    "s_cmp_eq_u32 s96, 0\n"                                                                               \
+    "s_add_u32 s94, s94, 224\n"                                                                           \
+    "s_addc_u32 s95, s95, 0\n"                                                                            \
+    "s_sub_u32 s96, s96, 1\n"                                                                             \
     "s_cbranch_scc0 fes_rg_loop_%=\n"                                                                     \
-    "fes_rg_end_%=:\n"
+    "fes_rg_end_%=:\n"                                                                                    \
+    "s_waitcnt lgkmcnt(0)\n"                                                                              \
+    "s_set_gpr_idx_off\n"                                                                                 \
+    "s_branch fes_rg_exit_%=\n"                                                                           \
+    FES_RG_REGS_A(FES_RG_MARKED) FES_RG_REGS_B(FES_RG_MARKED)                                             \
+    "fes_rg_exit_%=:\n"
 
 #define FES_RG_SCLOB                                                                                      \
     "m0", "scc", "s36", "s37", "s38", "s39", "s40", "s41", "s42", "s43", "s44", "s45", "s46", "s47", "s48",  \
@@ -417,16 +441,19 @@ constexpr int kFileBase = 24;
         "s91", "s92", "s93", "s94", "s95", "s96", "s97", "s98", "s99"
 #define FES_V10(d) "v" #d "0", "v" #d "1", "v" #d "2", "v" #d "3", "v" #d "4", "v" #d "5", "v" #d "6", \
                    "v" #d "7", "v" #d "8", "v" #d "9"
-// v16..v119 (file rows 0..95)
-#define FES_RG_VCLOB_96                                                                                   \
+// v16..v127 (file rows 0..103)
+#define FES_RG_VCLOB_104                                                                                  \
     "v16", "v17", "v18", "v19", FES_V10(2), FES_V10(3), FES_V10(4), FES_V10(5), FES_V10(6), FES_V10(7),     \
-        FES_V10(8), FES_V10(9), FES_V10(10), FES_V10(11)
-// v16..v159 (file rows 0..135)
-#define FES_RG_VCLOB_136 FES_RG_VCLOB_96, FES_V10(12), FES_V10(13), FES_V10(14), FES_V10(15)
+        FES_V10(8), FES_V10(9), FES_V10(10), FES_V10(11), "v120", "v121", "v122", "v123", "v124", "v125",   \
+        "v126", "v127"
+// v16..v167 (file rows 0..143)
+#define FES_RG_VCLOB_144                                                                                  \
+    FES_RG_VCLOB_104, "v128", "v129", FES_V10(13), FES_V10(14), FES_V10(15), "v160", "v161", "v162", "v163", \
+        "v164", "v165", "v166", "v167"
 // v16..v255 (file rows 0..231)
-#define FES_RG_VCLOB_232 FES_RG_VCLOB_136, FES_V10(16), FES_V10(17), FES_V10(18), FES_V10(19), FES_V10(20), \
-                         FES_V10(21), FES_V10(22), FES_V10(23), FES_V10(24), "v250", "v251", "v252", "v253",   \
-                         "v254", "v255"
+#define FES_RG_VCLOB_232                                                                                  \
+    FES_RG_VCLOB_144, "v168", "v169", FES_V10(17), FES_V10(18), FES_V10(19), FES_V10(20), FES_V10(21),     \
+        FES_V10(22), FES_V10(23), FES_V10(24), "v250", "v251", "v252", "v253", "v254", "v255"
 
 template <int R>
 __device__ __forceinline__ uint32_t regs_pass(const Instr* prog, uint32_t nb, uint32_t n, uint64_t base,
@@ -437,10 +464,10 @@ __device__ __forceinline__ uint32_t regs_pass(const Instr* prog, uint32_t nb, ui
     : [m] "=&v"(m)                                                                                        \
     : [prog] "s"(prog), [nb] "s"(nb), [n] "s"(n), [base] "s"(base), [x5] "v"(x5), [x6] "v"(x6),            \
       [x7] "v"(x7), [x8] "v"(x8), [x9] "v"(x9), [x10] "v"(x10)
-    if constexpr (R == 96) {
-        asm volatile(FES_RG_PASS_ASM FES_RG_OPERANDS : FES_RG_SCLOB, FES_RG_VCLOB_96);
-    } else if constexpr (R == 136) {
-        asm volatile(FES_RG_PASS_ASM FES_RG_OPERANDS : FES_RG_SCLOB, FES_RG_VCLOB_136);
+    if constexpr (R == 104) {
+        asm volatile(FES_RG_PASS_ASM FES_RG_OPERANDS : FES_RG_SCLOB, FES_RG_VCLOB_104);
+    } else if constexpr (R == 144) {
+        asm volatile(FES_RG_PASS_ASM FES_RG_OPERANDS : FES_RG_SCLOB, FES_RG_VCLOB_144);
     } else {
         asm volatile(FES_RG_PASS_ASM FES_RG_OPERANDS : FES_RG_SCLOB, FES_RG_VCLOB_232);
     }
@@ -504,12 +531,144 @@ hipError_t launch_regs(const InterpLaunch& L, int grid, hipStream_t stream) {
     return hipGetLastError();
 }
 
+// ---- register tier, simulation mode --------------------------------------------------------
+//
+// The logic simulation that opens a sweeping flow (Section 2.3, step 1) with the value file in
+// VGPRs: every variable's word is stored to its signature row, so the kernel is bound by HBM
+// writes rather than by instruction issue.  One pass covers 64 caller words (one per lane).
+// The stream (encode_sim_regs_stream) has the register tier's 28-word bundles with the XOR
+// masks and output flags replaced by the absolute address of each gate's signature row (two
+// words per gate; gates that define no variable point at a dummy row); it is built per call,
+// since the addresses depend on the signature buffer and its row length.  A pass: row 0 (zero)
+// and the n input rows are written to the file and stored, then per bundle the eight operand
+// reads with their complements, four ANDs, four indexed writes and four row stores.  Lanes past
+// the last word are masked off for the whole pass (EXEC), so they neither compute nor store.
+#define FES_RS_BUNDLE(a0, a1, a2, a3, b0, b1, b2, b3, d0, d1, d2, d3, ca0, ca1, ca2, ca3, cb0, cb1, cb2, cb3, P0, P1, \
+                      P2, P3)                                                                                        \
+    FES_RG_READS(a0, b0, a1, b1, a2, b2, a3, b3, ca0, cb0, ca1, cb1, ca2, cb2, ca3, cb3)                               \
+    "s_set_gpr_idx_off\n"                                                                                              \
+    "v_and_b32 v16, v16, v17\n"                                                                                        \
+    "v_and_b32 v18, v18, v19\n"                                                                                        \
+    "v_and_b32 v20, v20, v21\n"                                                                                        \
+    "v_and_b32 v22, v22, v23\n"                                                                                        \
+    FES_RG_WRITES(d0, d1, d2, d3)                                                                                      \
+    "global_store_dword %[off], v16, " P0 "\n"                                                                         \
+    "global_store_dword %[off], v18, " P1 "\n"                                                                         \
+    "global_store_dword %[off], v20, " P2 "\n"                                                                         \
+    "global_store_dword %[off], v22, " P3 "\n"
+#define FES_RS_BUF_A                                                                                           \
+    FES_RS_BUNDLE("s36", "s37", "s38", "s39", "s40", "s41", "s42", "s43", "s44", "s45", "s46", "s47", "s48", "s49", \
+                  "s50", "s51", "s52", "s53", "s54", "s55", "s[56:57]", "s[58:59]", "s[60:61]", "s[62:63]")
+#define FES_RS_BUF_B                                                                                           \
+    FES_RS_BUNDLE("s64", "s65", "s66", "s67", "s68", "s69", "s70", "s71", "s72", "s73", "s74", "s75", "s76", "s77", \
+                  "s78", "s79", "s80", "s81", "s82", "s83", "s[84:85]", "s[86:87]", "s[88:89]", "s[90:91]")
+
+// Registers: s[92:93] address of the next input's signature row; s[94:95] stream pointer; s96
+// bundles left after the current one; s97 input row; s[98:99] address of the next input's
+// caller row.  The input loop waits for each load (vmcnt also counts the stores in flight); the
+// last stream prefetch is waited for before the statement ends.
+#define FES_RS_PASS_ASM                                                                                   \
+    "v_mov_b32 v24, 0\n"                                                                                  \
+    "global_store_dword %[off], v24, %[sig]\n"                                                            \
+    "s_cmp_eq_u32 %[n], 0\n"                                                                             \
+    "s_cbranch_scc1 fes_rs_in_done_%=\n"                                                                  \
+    "s_mov_b64 s[98:99], %[pi]\n"                                                                         \
+    "s_add_u32 s92, %[sig_lo], %[wb_lo]\n"                                                                \
+    "s_addc_u32 s93, %[sig_hi], %[wb_hi]\n"                                                               \
+    "s_mov_b32 s97, 1\n"                                                                                  \
+    "fes_rs_in_loop_%=:\n"                                                                                \
+    "global_load_dword v16, %[off], s[98:99]\n"                                                           \
+    "s_add_u32 s98, s98, %[wb_lo]\n"                                                                      \
+    "s_addc_u32 s99, s99, %[wb_hi]\n"                                                                     \
+    "s_waitcnt vmcnt(0)\n"                                                                                \
+    "s_set_gpr_idx_on s97, gpr_idx(DST)\n"                                                                \
+    "v_mov_b32 v24, v16\n"                                                                                \
+    "s_set_gpr_idx_off\n"                                                                                 \
+    "global_store_dword %[off], v16, s[92:93]\n"                                                          \
+    "s_add_u32 s92, s92, %[wb_lo]\n"                                                                      \
+    "s_addc_u32 s93, s93, %[wb_hi]\n"                                                                     \
+    "s_add_u32 s97, s97, 1\n"                                                                             \
+    "s_cmp_le_u32 s97, %[n]\n"                                                                            \
+    "s_cbranch_scc1 fes_rs_in_loop_%=\n"                                                                  \
+    "fes_rs_in_done_%=:\n"                                                                                \
+    "s_mov_b64 s[94:95], %[prog]\n"                                                                       \
+    "s_sub_u32 s96, %[nb], 1\n"                                                                           \
+    FES_RG_LOAD_A("0x0", "0x40", "0x60")                                                                  \
+    "fes_rs_loop_%=:\n"                                                                                   \
+    "s_waitcnt lgkmcnt(0)\n"                                                                              \
+    FES_RG_LOAD_B("0x70", "0xb0", "0xd0")                                                                 \
+    FES_RS_BUF_A                                                                                          \
+    "s_sub_u32 s96, s96, 1\n"                                                                             \
+    "s_cbranch_scc1 fes_rs_end_%=\n"                                                                      \
+    "s_waitcnt lgkmcnt(0)\n"                                                                              \
+    FES_RG_LOAD_A("0xe0", "0x120", "0x140")                                                               \
+    FES_RS_BUF_B                                                                                          \
+    "s_add_u32 s94, s94, 224\n"                                                                           \
+    "s_addc_u32 s95, s95, 0\n"                                                                            \
+    "s_sub_u32 s96, s96, 1\n"                                                                             \
+    "s_cbranch_scc0 fes_rs_loop_%=\n"                                                                     \
+    "fes_rs_end_%=:\n"                                                                                    \
+    "s_waitcnt lgkmcnt(0)\n"
+
+template <int R>
+__device__ __forceinline__ void sim_regs_pass(const uint32_t* prog, uint32_t nb, uint32_t n, const uint32_t* pi,
+                                              uint32_t* sig, uint32_t sig_lo, uint32_t sig_hi, uint32_t wb_lo,
+                                              uint32_t wb_hi, uint32_t off) {
+#define FES_RS_OPERANDS                                                                                   \
+    :                                                                                                     \
+    : [prog] "s"(prog), [nb] "s"(nb), [n] "s"(n), [pi] "s"(pi), [sig] "s"(sig), [sig_lo] "s"(sig_lo),      \
+      [sig_hi] "s"(sig_hi), [wb_lo] "s"(wb_lo), [wb_hi] "s"(wb_hi), [off] "v"(off)
+    if constexpr (R == 104) {
+        asm volatile(FES_RS_PASS_ASM FES_RS_OPERANDS : "memory", FES_RG_SCLOB, FES_RG_VCLOB_104);
+    } else if constexpr (R == 144) {
+        asm volatile(FES_RS_PASS_ASM FES_RS_OPERANDS : "memory", FES_RG_SCLOB, FES_RG_VCLOB_144);
+    } else {
+        asm volatile(FES_RS_PASS_ASM FES_RS_OPERANDS : "memory", FES_RG_SCLOB, FES_RG_VCLOB_232);
+    }
+#undef FES_RS_OPERANDS
+}
+
+template <int R, int kWaves>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWaves, kWaves)))
+es_sim_regs_kernel(InterpLaunch L) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t waves = gridDim.x;
+    const uint32_t nclaim = waves < kClaimCounters ? waves : kClaimCounters;
+    const uint32_t claim = __builtin_amdgcn_readfirstlane(blockIdx.x % nclaim);
+    unsigned long long* const counter = &L.ctl->next_item[claim * kClaimStride];
+    const FES_CONST ConeDesc* c = as_const(L.cones);
+    const uint32_t n = __builtin_amdgcn_readfirstlane(c->n_inputs);
+    const uint32_t nb = __builtin_amdgcn_readfirstlane(c->n_instr / 4u);
+    const uint32_t* prog = (const uint32_t*)c->prog;
+    const uint64_t W = L.sim_words, tile = c->tile_hw;
+    const uint64_t wb = W * 4u;
+    const uint64_t sig = (uint64_t)L.sim_sig;
+    for (;;) {
+        const uint64_t k = uniform64(atomicAdd(counter, lane == 0 ? 1ull : 0ull));
+        const uint64_t item = claim + k * nclaim;
+        if (item >= L.total_items) break;
+        const uint64_t hw0 = item * tile, hw_stop = min(hw0 + tile, W);
+        for (uint64_t base = hw0; base < hw_stop; base += 64u) {
+            const uint64_t w = base + lane;
+            if (w < W)
+                sim_regs_pass<R>(prog, nb, n, L.sim_pi, L.sim_sig, (uint32_t)sig, (uint32_t)(sig >> 32), (uint32_t)wb,
+                                 (uint32_t)(wb >> 32), (uint32_t)(w * 4u));
+        }
+    }
+}
+
+template <int R, int kWaves>
+hipError_t launch_sim_regs_t(const InterpLaunch& L, int grid, hipStream_t stream) {
+    hipLaunchKernelGGL((es_sim_regs_kernel<R, kWaves>), dim3(grid), dim3(64), 0, stream, L);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 int interp_regs_rows(uint32_t rows, int* waves_per_simd) {
     int w = 0, r = 0;
-    if (rows <= 96) { r = 96; w = 4; }
-    else if (rows <= 136) { r = 136; w = 3; }
+    if (rows <= 104) { r = 104; w = 4; }
+    else if (rows <= 144) { r = 144; w = 3; }
     else if (rows <= 232) { r = 232; w = 2; }
     if (waves_per_simd) *waves_per_simd = w;
     return r;
@@ -518,9 +677,20 @@ int interp_regs_rows(uint32_t rows, int* waves_per_simd) {
 hipError_t launch_interp_regs(const InterpLaunch& L, int regs, int grid, hipStream_t stream) {
     if (L.num_cones == 0 || grid <= 0 || L.rows_max > (uint32_t)regs) return hipErrorInvalidValue;
     switch (regs) {
-        case 96: return launch_regs<96, 4>(L, grid, stream);
-        case 136: return launch_regs<136, 3>(L, grid, stream);
+        case 104: return launch_regs<104, 4>(L, grid, stream);
+        case 144: return launch_regs<144, 3>(L, grid, stream);
         case 232: return launch_regs<232, 2>(L, grid, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_sim_regs(const InterpLaunch& L, int regs, int grid, hipStream_t stream) {
+    if (L.num_cones != 1 || !L.sim_sig || grid <= 0 || L.rows_max > (uint32_t)regs) return hipErrorInvalidValue;
+    if (L.sim_words == 0 || L.sim_words > (1ull << 30)) return hipErrorInvalidValue;  // 32-bit byte offsets
+    switch (regs) {
+        case 104: return launch_sim_regs_t<104, 4>(L, grid, stream);
+        case 144: return launch_sim_regs_t<144, 3>(L, grid, stream);
+        case 232: return launch_sim_regs_t<232, 2>(L, grid, stream);
         default: return hipErrorInvalidValue;
     }
 }

@@ -83,11 +83,21 @@ hipError_t launch_signature_hash(const uint32_t* sig, uint64_t rows, uint64_t wo
 //   xm[4]  XOR masks (all ones for a fused three-AND XOR, else 0),
 //   fl[4]  the instruction flags (output polarity bits 0 and 1), read only in marked bundles.
 constexpr uint32_t kRegsBundleWords = 28;
-// Encode a bundled plan (bundle 4) into that layout.
+// Encode a bundled plan (bundle 4) into that layout, followed by one bundle of zeros (the kernel
+// prefetches one bundle past the one it runs, so the last prefetch stays inside the stream).
 void encode_regs_stream(const Plan& p, std::vector<uint32_t>& out);
 
+// The simulation-mode variant of that layout for one call: words 20..27 hold, per gate, the
+// 64-bit address of the signature row of the variable it defines (sig + variable * words), or
+// `dummy` (a row of `words` words) for instructions that define none; one zero bundle follows.
+void encode_sim_regs_stream(const Plan& p, const uint32_t* sig, uint64_t words, const uint32_t* dummy,
+                            std::vector<uint32_t>& out);
+// Simulation mode in the register tier: one cone, the stream above as the descriptor's prog,
+// columns [0, sim_words) (at most 2^30) simulated once each; `regs` as for launch_interp_regs.
+hipError_t launch_sim_regs(const InterpLaunch& L, int regs, int grid, hipStream_t stream);
+
 // Register tier: value files in VGPRs (one wave per workgroup, bundles of 4, one 32-bit word per
-// lane).  interp_regs_rows: the file size (96, 136 or 232 rows) that holds `rows`, 0 if none
+// lane).  interp_regs_rows: the file size (104, 144 or 232 rows) that holds `rows`, 0 if none
 // does, with the waves per SIMD it allows.  launch_interp_regs: `regs` is that file size.
 int interp_regs_rows(uint32_t rows, int* waves_per_simd);
 hipError_t launch_interp_regs(const InterpLaunch& L, int regs, int grid, hipStream_t stream);

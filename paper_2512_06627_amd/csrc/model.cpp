@@ -11,7 +11,7 @@ namespace fes {
 // that holds the value file.
 namespace model {
 constexpr double kInterpT0Ms = 0.0120;
-constexpr uint32_t kTierRows[3] = {96, 136, 232};  // register tier files; LDS or device memory above
+constexpr uint32_t kTierRows[3] = {104, 144, 232};  // register tier files; LDS or device memory above
 constexpr double kInterpRate[4] = {1.345e14, 1.402e14, 1.260e14, 2.17e13};  // gate instructions*patterns/s
 constexpr double kInterpMsPerGateFloor = 3.16e-5; // one wave pass per gate: spaces below a chip's waves
 constexpr double kSpecT0Ms = 0.0135;

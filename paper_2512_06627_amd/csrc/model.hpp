@@ -12,13 +12,13 @@
 namespace fes {
 
 //  interpreter:  t = t0 + N * max(patterns / R, L), N = bundled-stream gate instructions,
-//                R by the value-file tier of its `rows` (register tier files of at most 96,
-//                136 and 232 rows at four, three and two waves per SIMD; LDS or device memory
+//                R by the value-file tier of its `rows` (register tier files of at most 104,
+//                144 and 232 rows at four, three and two waves per SIMD; LDS or device memory
 //                above), L = one wave pass per gate
 //  specialized:  t = t0 + LUT steps * passes / R, passes = patterns / 2048 (at least 1)
 //  compile:      t = c0 + c1 * LUT steps
 double model_interp_ms(uint32_t gates, uint32_t rows, double patterns);
-// Tier of a value file of `rows` rows: 0..2 register tier (96, 136, 232 rows), 3 LDS or device memory.
+// Tier of a value file of `rows` rows: 0..2 register tier (104, 144, 232 rows), 3 LDS or device memory.
 int model_interp_tier(uint32_t rows);
 double model_specialized_ms(uint32_t lut_steps, double patterns);
 double model_compile_ms(uint32_t lut_steps);

@@ -105,7 +105,9 @@ const Instr* Circuit::device_prog(int dev, uint32_t bundle, hipStream_t s) {
 
 void encode_regs_stream(const Plan& p, std::vector<uint32_t>& out) {
     if (p.bundle != 4 || p.prog.size() % 4) throw Error{kErrInvalid, "register-tier stream needs bundles of 4"};
-    out.assign(p.prog.size() / 4 * kRegsBundleWords, 0u);
+    // One zero bundle of padding after the last: the kernel loads the bundle after the current
+    // one unconditionally.
+    out.assign((p.prog.size() / 4 + 1) * kRegsBundleWords, 0u);
     for (size_t b = 0; b < p.prog.size() / 4; ++b) {
         uint32_t* w = out.data() + b * kRegsBundleWords;
         bool any_out = false;
@@ -121,6 +123,30 @@ void encode_regs_stream(const Plan& p, std::vector<uint32_t>& out) {
             any_out = any_out || (ins.flags & (kOutPos | kOutNeg));
         }
         if (any_out) w[8] |= 0x80000000u;
+    }
+}
+
+void encode_sim_regs_stream(const Plan& p, const uint32_t* sig, uint64_t words, const uint32_t* dummy,
+                            std::vector<uint32_t>& out) {
+    if (p.bundle != 4 || p.prog.size() % 4) throw Error{kErrInvalid, "register-tier stream needs bundles of 4"};
+    out.assign((p.prog.size() / 4 + 1) * kRegsBundleWords, 0u);
+    for (size_t b = 0; b < p.prog.size() / 4; ++b) {
+        uint32_t* w = out.data() + b * kRegsBundleWords;
+        for (int u = 0; u < 4; ++u) {
+            const size_t t = b * 4 + u;
+            const Instr& ins = p.prog[t];
+            w[u] = ins.a;
+            w[4 + u] = ins.b;
+            w[8 + u] = ins.d;
+            w[12 + u] = (ins.a & kCompl) ? ~0u : 0u;
+            w[16 + u] = (ins.b & kCompl) ? ~0u : 0u;
+            // variable defined by the instruction (gates only): its signature row, else the dummy row
+            const uint64_t addr = p.instr_gate[t] == UINT32_MAX
+                                      ? (uint64_t)dummy
+                                      : (uint64_t)(sig + (uint64_t)(p.num_inputs + 1 + p.instr_gate[t]) * words);
+            w[20 + 2 * u] = (uint32_t)addr;
+            w[21 + 2 * u] = (uint32_t)(addr >> 32);
+        }
     }
 }
 
@@ -148,7 +174,7 @@ const uint32_t* Circuit::device_regs_stream(int dev, hipStream_t s) {
 
 const Plan& Circuit::sim_plan(uint32_t bundle) {
     std::lock_guard<std::mutex> g(mu);
-    std::unique_ptr<Plan>& sim = this->sim[bundle];  // bundle 8 or 16
+    std::unique_ptr<Plan>& sim = this->sim[bundle];  // bundle 4 (register tier), 8 or 16
     if (!sim) {
         Aig all = aig;
         std::vector<uint8_t> read(all.max_var() + 1, 0);
@@ -512,8 +538,95 @@ void run_interp(Device& dev, const std::vector<Circuit*>& cs, const std::vector<
 
 namespace fes {
 
+namespace {
+
+// Simulation with the value file in VGPRs (register tier).  Returns false when the circuit's
+// simulation plan does not fit that tier, or the call asks for another schedule.
+bool run_sim_regs(Device& dev, Circuit& c, const uint32_t* pi, uint64_t words, uint32_t* sig,
+                  const fastlec_es_options* o, hipStream_t stream, double* kernel_ms) {
+    if (!regs_tier_enabled() || words > (1ull << 30)) return false;
+    if (o && (o->kernel == FASTLEC_KERNEL_INTERP_HBM || o->words_per_thread || o->wg_size)) return false;
+    const Plan& p = c.sim_plan(4);
+    int waves_per_simd = 0;
+    const int regs = interp_regs_rows(p.rows, &waves_per_simd);
+    if (!regs || p.prog.empty()) return false;
+    bool any_dummy = false;
+    for (uint32_t g : p.instr_gate) any_dummy = any_dummy || g == UINT32_MAX;
+
+    // One work item per pass of 64 words when passes are few, so the last round of claims is as
+    // full as it can be; a grid no larger than the passes need.
+    const uint64_t passes = (words + 63) / 64;
+    const uint64_t cap = (uint64_t)dev.prop.multiProcessorCount * 4 * waves_per_simd;
+    const uint64_t rounds = (passes + cap - 1) / cap;
+    const uint64_t grid = (passes + rounds - 1) / rounds;
+    uint64_t tile_passes = 1;
+    if (o && o->tile_words) tile_passes = std::max<uint64_t>(1, (2ull * o->tile_words + 63) / 64);
+    else
+        while (tile_passes < 16 && passes / (tile_passes * 2) >= grid * 16) tile_passes *= 2;
+
+    const size_t nbytes_stream = (p.prog.size() / 4 + 1) * kRegsBundleWords * sizeof(uint32_t);
+    Layout lay = layout(1, 0);
+    const size_t stream_off = lay.files_off;
+    const size_t dummy_off = (stream_off + nbytes_stream + 255) & ~size_t(255);
+    const size_t total = dummy_off + (any_dummy ? words * 4ull : 0);
+    Buffer buf = dev.acquire(total, dummy_off);
+    struct Releaser {
+        Device& d;
+        Buffer b;
+        ~Releaser() { d.release(b); }
+    } rel{dev, buf};
+    uint8_t* host = (uint8_t*)buf.host;
+    uint8_t* devp = (uint8_t*)buf.dev;
+    std::memset(host, 0, lay.files_off);
+    std::vector<uint32_t> st;
+    encode_sim_regs_stream(p, sig, words, (const uint32_t*)(devp + dummy_off), st);
+    std::memcpy(host + stream_off, st.data(), st.size() * sizeof(uint32_t));
+
+    ConeDesc& d = *(ConeDesc*)(host + lay.desc_off);
+    d.prog = (const Instr*)(devp + stream_off);
+    d.n_instr = (uint32_t)p.prog.size();
+    d.n_inputs = p.num_inputs;
+    d.rows = p.rows;
+    d.hw_begin = 0;
+    d.hw_end = words;
+    d.hw_first = 0;
+    d.tile_hw = 64ull * tile_passes;
+    d.item_begin = 0;
+    d.item_end = (words + d.tile_hw - 1) / d.tile_hw;
+
+    InterpLaunch L;
+    L.cones = (const ConeDesc*)(devp + lay.desc_off);
+    L.num_cones = 1;
+    L.rows_max = p.rows;
+    L.total_items = d.item_end;
+    L.ctl = (LaunchCtl*)devp;
+    L.best = (unsigned long long*)(devp + lay.best_off);
+    L.hbm_rows = nullptr;
+    L.cancel = nullptr;
+    L.sim_pi = pi;
+    L.sim_sig = sig;
+    L.sim_words = words;
+
+    ScopedEvent e0, e1;
+    trace("sim launch (registers): %llu words, %llu items of %llu passes, file %d rows, grid=%llu",
+          (unsigned long long)words, (unsigned long long)L.total_items, (unsigned long long)tile_passes, regs,
+          (unsigned long long)grid);
+    FES_HIP(hipMemcpyAsync(devp, host, dummy_off, hipMemcpyHostToDevice, stream));
+    FES_HIP(hipEventRecord(e0.e, stream));
+    FES_HIP(launch_sim_regs(L, regs, (int)grid, stream));
+    FES_HIP(hipEventRecord(e1.e, stream));
+    FES_HIP(hipStreamSynchronize(stream));
+    float ms = 0;
+    FES_HIP(hipEventElapsedTime(&ms, e0.e, e1.e));
+    if (kernel_ms) *kernel_ms = ms;
+    return true;
+}
+
+}  // namespace
+
 void run_sim(Device& dev, Circuit& c, const uint32_t* pi, uint64_t words, uint32_t* sig,
              const fastlec_es_options* o, hipStream_t stream, double* kernel_ms) {
+    if (run_sim_regs(dev, c, pi, words, sig, o, stream, kernel_ms)) return;
     // Bundles of 16 gates give each wave twice the independent LDS reads per wait (not with 4
     // words per lane, which spills registers).  Words per lane and workgroup size as for plain
     // checks: the most pattern words in flight per CU (16x16 miter, 2^18 words: 2.96 ms with

@@ -92,7 +92,8 @@ struct Circuit {
     uint32_t interp_rows() { return plan_for(4).rows; }
     // The register tier's stream: the plan in bundles of 4, each bundle kRegsBundleWords words
     // (operand and destination words, complement and XOR masks, output flags; see
-    // encode_regs_stream).  Host copy and per-device copies, built on first use.
+    // encode_regs_stream; one bundle of zero padding at the end).  Host copy and per-device
+    // copies, built on first use.
     const std::vector<uint32_t>& regs_stream();
     const uint32_t* device_regs_stream(int device, hipStream_t s);
     std::vector<uint32_t> regs_host;

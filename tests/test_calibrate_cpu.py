@@ -1,7 +1,7 @@
 """The runtime-model fit (paper_2512_06627_amd/calibrate.py) recovers known constants.
 
 Times are generated from the model's own form with chosen constants (interpreter: launch
-cost, one rate per value-file tier (register tier files of 96, 136, 232 rows, LDS above), a
+cost, one rate per value-file tier (register tier files of 104, 144, 232 rows, LDS above), a
 per-gate floor; specialized: launch cost and a
 rate over LUT steps x passes; compile: fixed plus per-LUT cost) and perturbed by a seeded 3%
 noise; the fit must return the constants within a few percent.  No GPU involved.
@@ -18,7 +18,7 @@ def synthetic(seed=7):
     s0, s_rate, c0, c1 = 0.013, 6e11, 105.0, 0.0065
     rows = []
     for n in (12, 14, 16, 18, 20, 22, 24, 26, 28):
-        for N in (300, 1000, 3000, 8000, 14000):
+        for N in (300, 1000, 3000, 5000, 8000, 14000):  # value files of 46..320 rows: every tier
             slots = 40 + N // 50
             luts = N // 3
             P = 2.0 ** n

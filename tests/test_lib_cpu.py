@@ -81,8 +81,9 @@ def _replay_vs_oracle(g, bundle, halfwords):
         assert word == int(sum(int(b) << j for j, b in enumerate(bits))), (hw, bundle)
 
 
-@pytest.mark.parametrize("bundle", [1, 4, 8, 16])
+@pytest.mark.parametrize("bundle", [0, 1, 4, 8, 16])
 def test_plan_replay_matches_oracle(bundle):
+    # bundle 0: the register tier's encoded stream, read the way that kernel reads it
     rng = miters.SplitMix64(bundle)
     for name in ("mult6_array_wallace_f1", "mult12_array_booth_f3", "mac8_fused_separate_f1"):
         g = miters.workload(name)
@@ -271,3 +272,24 @@ def test_xor_fusion_count_matches_definition(name):
     g = miters.workload(name)
     c = es.fastlec_es_load_aig(g.to_aig())
     assert c.info()["num_xors"] == _xor_roots(g) > 0
+
+
+def test_register_stream_replay_on_wide_files_and_limits():
+    # Value files near each register-tier size (104, 144, 232 rows) replay like the oracle; a
+    # file above 232 rows is refused.
+    rng = miters.SplitMix64(77)
+    seen = set()
+    for seed, n, gates in ((41, 16, 1200), (43, 18, 7000), (44, 20, 8000), (46, 16, 20000)):
+        g = miters.layered_cone_miter(seed, n, gates, fault_seed=seed)
+        rows = es.fastlec_es_load_aig(g.to_aig()).info()["interp_rows"]
+        if rows > 232:
+            with pytest.raises(es.EsError) as ei:
+                es.fastlec_es_host_replay(es.fastlec_es_load_aig(g.to_aig()), 0, 0, 1)
+            assert ei.value.code == es.FASTLEC_ERR_INVALID
+            seen.add("over")
+            continue
+        seen.add(104 if rows <= 104 else 144 if rows <= 144 else 232)
+        _replay_vs_oracle(g, 0, [rng.below(1 << (n - 5)) for _ in range(4)])
+    g = miters.workload("mult16_array_booth_f1")
+    _replay_vs_oracle(g, 0, [0, (1 << 27) - 1, rng.below(1 << 27)])
+    assert seen == {104, 144, 232, "over"}, seen
