@@ -160,7 +160,7 @@ def batch_leg(es, stream, seed: int = 4, count: int = 256, faulty: int = 26, n_r
             "batched_cones_per_s": count / t_batch, "batched_vs_plain_speedup": t_plain / t_batch,
             "plain_auto_cones_per_s": count / t_plain_auto, "batched_vs_plain_auto_speedup": t_plain_auto / t_batch,
             "identical_verdicts": plain == plain2 == interp_first == got_interp == first == got == plain_auto,
-            "first_batch_call_s": t_first, "generate_s": gen_s}
+            "first_batch_call_s": t_first, "first_batch_call_cones_per_s": count / t_first, "generate_s": gen_s}
 
 
 def interp_leg(es, stream, seed: int = 4, count: int = 256, faulty: int = 26, n_range=(18, 30),

@@ -543,6 +543,8 @@ hipError_t launch_regs(const InterpLaunch& L, int grid, hipStream_t stream) {
 // and the n input rows are written to the file and stored, then per bundle the eight operand
 // reads with their complements, four ANDs, four indexed writes and four row stores.  Lanes past
 // the last word are masked off for the whole pass (EXEC), so they neither compute nor store.
+// The stores are non-temporal: the signature matrix is far larger than the caches and is read
+// back by a later kernel (16x16 miter at 2^18 words: 1.87 ms with ordinary stores, 1.45 ms).
 #define FES_RS_BUNDLE(a0, a1, a2, a3, b0, b1, b2, b3, d0, d1, d2, d3, ca0, ca1, ca2, ca3, cb0, cb1, cb2, cb3, P0, P1, \
                       P2, P3)                                                                                        \
     FES_RG_READS(a0, b0, a1, b1, a2, b2, a3, b3, ca0, cb0, ca1, cb1, ca2, cb2, ca3, cb3)                               \
@@ -552,10 +554,10 @@ hipError_t launch_regs(const InterpLaunch& L, int grid, hipStream_t stream) {
     "v_and_b32 v20, v20, v21\n"                                                                                        \
     "v_and_b32 v22, v22, v23\n"                                                                                        \
     FES_RG_WRITES(d0, d1, d2, d3)                                                                                      \
-    "global_store_dword %[off], v16, " P0 "\n"                                                                         \
-    "global_store_dword %[off], v18, " P1 "\n"                                                                         \
-    "global_store_dword %[off], v20, " P2 "\n"                                                                         \
-    "global_store_dword %[off], v22, " P3 "\n"
+    "global_store_dword %[off], v16, " P0 " nt\n"                                                                         \
+    "global_store_dword %[off], v18, " P1 " nt\n"                                                                         \
+    "global_store_dword %[off], v20, " P2 " nt\n"                                                                         \
+    "global_store_dword %[off], v22, " P3 " nt\n"
 #define FES_RS_BUF_A                                                                                           \
     FES_RS_BUNDLE("s36", "s37", "s38", "s39", "s40", "s41", "s42", "s43", "s44", "s45", "s46", "s47", "s48", "s49", \
                   "s50", "s51", "s52", "s53", "s54", "s55", "s[56:57]", "s[58:59]", "s[60:61]", "s[62:63]")
@@ -569,7 +571,7 @@ hipError_t launch_regs(const InterpLaunch& L, int grid, hipStream_t stream) {
 // last stream prefetch is waited for before the statement ends.
 #define FES_RS_PASS_ASM                                                                                   \
     "v_mov_b32 v24, 0\n"                                                                                  \
-    "global_store_dword %[off], v24, %[sig]\n"                                                            \
+    "global_store_dword %[off], v24, %[sig] nt\n"                                                            \
     "s_cmp_eq_u32 %[n], 0\n"                                                                             \
     "s_cbranch_scc1 fes_rs_in_done_%=\n"                                                                  \
     "s_mov_b64 s[98:99], %[pi]\n"                                                                         \
@@ -584,7 +586,7 @@ hipError_t launch_regs(const InterpLaunch& L, int grid, hipStream_t stream) {
     "s_set_gpr_idx_on s97, gpr_idx(DST)\n"                                                                \
     "v_mov_b32 v24, v16\n"                                                                                \
     "s_set_gpr_idx_off\n"                                                                                 \
-    "global_store_dword %[off], v16, s[92:93]\n"                                                          \
+    "global_store_dword %[off], v16, s[92:93] nt\n"                                                          \
     "s_add_u32 s92, s92, %[wb_lo]\n"                                                                      \
     "s_addc_u32 s93, s93, %[wb_hi]\n"                                                                     \
     "s_add_u32 s97, s97, 1\n"                                                                             \
