@@ -214,7 +214,9 @@ typedef struct {
  * device-resident job table between steps.  A job whose remaining interpreter time is
  * estimated well above the time to compile its specialized kernel is compiled on a
  * background thread meanwhile; its later slices run on that kernel (same ascending slices,
- * same answer).  FASTLEC_ES_SERVER_JIT=0 turns this off.  opts: device, stream, schedule
+ * same answer).  FASTLEC_ES_SERVER_JIT=0 turns this off.  Slices are sized for steps of
+ * FASTLEC_ES_SERVER_STEP_MS (default 10) ms from a running rate estimate that starts at
+ * FASTLEC_ES_SERVER_RATE node*patterns/s (default 1e14).  opts: device, stream, schedule
  * fields; the word range, deadline and cancel fields are ignored.  budget_bytes > 0. */
 int fastlec_es_server_create(const fastlec_es_options *opts, size_t budget_bytes, fastlec_es_server **out);
 

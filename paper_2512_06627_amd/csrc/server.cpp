@@ -309,7 +309,8 @@ void fastlec_es_server::step(const std::vector<Job*>& act) {
             }
         }
         if (!have) g.sch = shrink_schedule(*dev, *g.c, &o, kB);
-        if (!g.sch.lds) {
+        const bool files_needed = !g.sch.lds && !g.sch.regs;  // the register and LDS tiers hold their own
+        if (files_needed) {
             // Value files in device memory: the grid is capped so that the server's device
             // memory (job table plus files) stays within the budget.
             const size_t per_block = (size_t)(g.sch.block / 64) * rows_for(*g.c, kB) * 64ull * g.sch.K * 4ull;
@@ -320,16 +321,23 @@ void fastlec_es_server::step(const std::vector<Job*>& act) {
             g.sch.grid = (int)std::min<size_t>((size_t)g.sch.grid, fit);
         }
         g.items = build_descs(*dev, *g.c, *g.r, *g.i, g.sch, stream, (ConeDesc*)(host + g.desc_off));
-        if (!g.sch.lds) {
+        if (files_needed) {
             const size_t need = (size_t)g.sch.grid * (g.sch.block / 64) * rows_for(*g.c, kB) * 64ull * g.sch.K * 4ull;
             if (files.bytes < need) {  // device-only, exactly sized (not pooled), within the budget
-                if (files.dev) (void)hipFree(files.dev);
-                files = Buffer{};
-                const size_t bytes = (need + 4095) & ~size_t(4095);
-                if (hipMalloc(&files.dev, bytes) != hipSuccess) {
-                    files.dev = nullptr;
-                    throw Error{kErrNoMem, "device allocation of the server's value files failed"};
+                // files is read by stats callers under mu: swap it under the lock, allocate outside
+                void* old = nullptr;
+                {
+                    std::lock_guard<std::mutex> lk(mu);
+                    old = files.dev;
+                    files = Buffer{};
                 }
+                if (old) (void)hipFree(old);
+                const size_t bytes = (need + 4095) & ~size_t(4095);
+                void* fresh = nullptr;
+                if (hipMalloc(&fresh, bytes) != hipSuccess)
+                    throw Error{kErrNoMem, "device allocation of the server's value files failed"};
+                std::lock_guard<std::mutex> lk(mu);
+                files.dev = fresh;
                 files.bytes = bytes;
             }
         }
@@ -351,7 +359,7 @@ void fastlec_es_server::step(const std::vector<Job*>& act) {
         L.total_items = g.items;
         L.ctl = (LaunchCtl*)(devp + g.ctl_off);
         L.best = (unsigned long long*)(devp + off_best);
-        L.hbm_rows = g.sch.lds ? nullptr : (uint32_t*)files.dev;
+        L.hbm_rows = (g.sch.lds || g.sch.regs) ? nullptr : (uint32_t*)files.dev;
         L.cancel = nullptr;
         FES_HIP(launch_schedule(L, g.sch, stream));
     }
@@ -504,6 +512,8 @@ int fastlec_es_server_create(const fastlec_es_options* opts, size_t budget_bytes
         s->budget = budget_bytes;
         s->chunk_words = std::max<uint64_t>(1, env_u64("FASTLEC_ES_SERVER_CHUNK_WORDS", 1ull << 22));
         s->step_ms_target = (double)std::max<uint64_t>(1, env_u64("FASTLEC_ES_SERVER_STEP_MS", 10));
+        // initial interpreter rate estimate (node*patterns/s) from which the first slices are sized
+        if (const uint64_t r0 = env_u64("FASTLEC_ES_SERVER_RATE", 0)) s->rate = (double)r0;
         s->dev = &device(s->opts.device);
         s->stream = s->opts.hip_stream ? (hipStream_t)s->opts.hip_stream : s->dev->stream;
         s->jit_mode = (int)std::min<uint64_t>(2, env_u64("FASTLEC_ES_SERVER_JIT", 1));
