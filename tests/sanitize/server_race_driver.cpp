@@ -5,7 +5,8 @@
 // the jobs that carry most of the work).  This driver runs them against each other: several
 // submitter threads, poller threads that take tickets from the submitters, a stats reader, and a
 // second server destroyed while jobs and compiles are still in flight.  Every answer must equal
-// the same circuit checked alone with fastlec_es_check.
+// the same circuit checked alone with fastlec_es_check.  In between, four threads run plain
+// checks (each kernel choice) and predictions on the same handles at once.
 //
 // Built with -fsanitize=thread together with the library's host sources and fake_device.cpp
 // (a host stand-in for the GPU: the HIP runtime finds no device in a process built with the
@@ -157,6 +158,29 @@ int main(int argc, char** argv) {
                 done.load(), mismatches.load(), errors.load(), (unsigned long long)st.specialized_slices,
                 (unsigned long long)st.steps);
     if (done.load() != total || mismatches.load() || errors.load()) return fail("server answers", 0);
+
+    // Plain checks of the same handles from several threads at once (the header allows it):
+    // plan, stream and kernel caches, the device's buffer pool and the runtime model.
+    std::atomic<int> plain_bad{0};
+    std::vector<std::thread> pt;
+    for (int t = 0; t < 4; ++t)
+        pt.emplace_back([&, t] {
+            for (int round = 0; round < 2; ++round)
+                for (size_t k = 0; k < cs.size(); ++k) {
+                    const size_t i = (k + (size_t)t) % cs.size();
+                    fastlec_es_options po;
+                    fastlec_es_options_init(&po);
+                    po.kernel = (t + round) % 3 == 0 ? FASTLEC_KERNEL_AUTO
+                                : (t + round) % 3 == 1 ? FASTLEC_KERNEL_INTERP : FASTLEC_KERNEL_SPECIALIZED;
+                    fastlec_es_result r;
+                    if (fastlec_es_check(cs[i], &po, &r) || answer(r) != want[i]) plain_bad.fetch_add(1);
+                    double pi = 0, ps = 0, pc = 0;
+                    if (fastlec_es_predict(cs[i], 0, 0, &pi, &ps, &pc)) plain_bad.fetch_add(1);
+                }
+        });
+    for (auto& t : pt) t.join();
+    std::printf("plain checks from 4 threads: %d wrong\n", plain_bad.load());
+    if (plain_bad.load()) return fail("concurrent plain checks", 0);
 
     // Teardown with work in flight: jobs queued and running, compiles possibly under way.
     rc = fastlec_es_server_create(&o, size_t(64) << 30, &srv);
