@@ -246,12 +246,33 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
                 spec.push_back(i);
             }
         } else if (o.kernel == FASTLEC_KERNEL_AUTO) {
-            double saving = 0;
+            // First an optimistic bound (a LUT count below any cover measured) over the cones that
+            // could pay for a compile share: when even that saving cannot pay for one program, only
+            // cones whose kernels already exist are considered, and no LUT program is built.
+            std::vector<size_t> cand;
+            std::vector<double> tis;
+            double optimistic = 0;
             for (size_t i = 0; i < k; ++i) {
                 Circuit& c = *v[i];
                 const double patterns = 32.0 * (double)(rs[i].end - rs[i].begin);
                 const double ti = model_interp_ms(c.interp_gates(), c.interp_rows(), patterns);
                 if (ti < kCompileMargin * (model_compile_ms(0) / 64.0)) continue;  // cheap cone: no LUT program
+                cand.push_back(i);
+                tis.push_back(ti);
+                const uint32_t lo = model_lut_steps_low(c.plan1.num_ands_tfi);
+                const double ts = model_specialized_ms(lo, patterns);
+                const double own = jit_ready(c, specialized_waves_per_eu()) ? 0.0
+                                   : kCompileMargin * (model_compile_ms(lo) - model_compile_ms(0));
+                if (ts + own < ti) optimistic += ti - ts - own;
+            }
+            const bool program_possible = optimistic >= kCompileMargin * model_compile_ms(0);
+            double saving = 0;
+            for (size_t ci = 0; ci < cand.size(); ++ci) {
+                const size_t i = cand[ci];
+                Circuit& c = *v[i];
+                const double patterns = 32.0 * (double)(rs[i].end - rs[i].begin);
+                const double ti = tis[ci];
+                if (!program_possible && !jit_ready(c, specialized_waves_per_eu())) continue;
                 const uint32_t luts = c.lut_program().lut_steps;
                 const double ts = model_specialized_ms(luts, patterns);
                 const double own = jit_ready(c, specialized_waves_per_eu()) ? 0.0

@@ -19,6 +19,7 @@ constexpr double kSpecLutPassesPerS = 6.31e11;
 constexpr double kCompileC0Ms = 103.9;
 constexpr double kCompileMsPerLut = 0.00660;
 constexpr double kLutsPerGate = 0.30;
+constexpr double kLutsPerGateLow = 0.20;  // below every cover measured (0.23 layered cones, 0.28 multipliers)
 }  // namespace model
 
 int model_interp_tier(uint32_t rows) {
@@ -40,6 +41,10 @@ double model_compile_ms(uint32_t lut_steps) { return model::kCompileC0Ms + model
 
 uint32_t model_lut_steps_estimate(uint32_t and_gates) {
     return (uint32_t)((double)and_gates * model::kLutsPerGate + 0.5);
+}
+
+uint32_t model_lut_steps_low(uint32_t and_gates) {
+    return std::max<uint32_t>(1, (uint32_t)((double)and_gates * model::kLutsPerGateLow));
 }
 
 double lpt_cost_ms(uint32_t interp_gates, uint32_t rows, double patterns) {

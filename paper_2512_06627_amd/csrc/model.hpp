@@ -27,6 +27,9 @@ double model_compile_ms(uint32_t lut_steps);
 // (measured covers: 0.28 LUTs per gate for the 16x16 multiplier miter, 0.23 for layered cones;
 // the larger ratio is used, so compiles are not underestimated).
 uint32_t model_lut_steps_estimate(uint32_t and_gates);
+// A count below the LUT steps of any cone measured (0.2 per AND gate): the specialized time and
+// compile it gives are optimistic, so a saving that cannot pay off with it cannot pay off at all.
+uint32_t model_lut_steps_low(uint32_t and_gates);
 
 // Longest-processing-time cost of a cone in a shared interpreter launch: its predicted
 // interpreter time over its range (ms).
