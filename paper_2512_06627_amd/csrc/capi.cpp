@@ -266,6 +266,11 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
                 if (ts + own < ti) optimistic += ti - ts - own;
             }
             const bool program_possible = optimistic >= kCompileMargin * model_compile_ms(0);
+            // The LUT programs the decision needs, mapped on host threads in parallel.
+            std::vector<Circuit*> mapped;
+            for (size_t i : cand)
+                if (program_possible || jit_ready(*v[i], specialized_waves_per_eu())) mapped.push_back(v[i]);
+            parallel_for(mapped.size(), [&](size_t t) { (void)mapped[t]->lut_program(); });
             double saving = 0;
             for (size_t ci = 0; ci < cand.size(); ++ci) {
                 const size_t i = cand[ci];

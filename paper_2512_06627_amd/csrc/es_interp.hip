@@ -566,33 +566,71 @@ hipError_t launch_regs(const InterpLaunch& L, int grid, hipStream_t stream) {
                   "s78", "s79", "s80", "s81", "s82", "s83", "s[84:85]", "s[86:87]", "s[88:89]", "s[90:91]")
 
 // Registers: s[92:93] address of the next input's signature row; s[94:95] stream pointer; s96
-// bundles left after the current one; s97 input row; s[98:99] address of the next input's
-// caller row.  The input loop waits for each load (vmcnt also counts the stores in flight); the
-// last stream prefetch is waited for before the statement ends.
+// bundles left after the current one; s[98:99] address of the next input's caller row.  The
+// input loads share one wait (vmcnt also counts the stores still in flight); the last stream
+// prefetch is waited for before the statement ends.
+// Input i (n <= 63) is loaded straight into its file row v(25 + i) and stored to its signature
+// row: all loads of a pass are issued before one wait.
+#define FES_RS_LD(I, V)                              \
+    "s_cmp_eq_u32 %[n], " #I "\n"                    \
+    "s_cbranch_scc1 fes_rs_ld_done_%=\n"              \
+    "global_load_dword " V ", %[off], s[98:99]\n"     \
+    "s_add_u32 s98, s98, %[wb_lo]\n"                 \
+    "s_addc_u32 s99, s99, %[wb_hi]\n"
+#define FES_RS_ST(I, V)                              \
+    "s_cmp_eq_u32 %[n], " #I "\n"                    \
+    "s_cbranch_scc1 fes_rs_st_done_%=\n"              \
+    "global_store_dword %[off], " V ", s[92:93] nt\n" \
+    "s_add_u32 s92, s92, %[wb_lo]\n"                 \
+    "s_addc_u32 s93, s93, %[wb_hi]\n"
+#define FES_RS_LOADS \
+    FES_RS_LD(0, "v25") FES_RS_LD(1, "v26") FES_RS_LD(2, "v27") FES_RS_LD(3, "v28") \
+    FES_RS_LD(4, "v29") FES_RS_LD(5, "v30") FES_RS_LD(6, "v31") FES_RS_LD(7, "v32") \
+    FES_RS_LD(8, "v33") FES_RS_LD(9, "v34") FES_RS_LD(10, "v35") FES_RS_LD(11, "v36") \
+    FES_RS_LD(12, "v37") FES_RS_LD(13, "v38") FES_RS_LD(14, "v39") FES_RS_LD(15, "v40") \
+    FES_RS_LD(16, "v41") FES_RS_LD(17, "v42") FES_RS_LD(18, "v43") FES_RS_LD(19, "v44") \
+    FES_RS_LD(20, "v45") FES_RS_LD(21, "v46") FES_RS_LD(22, "v47") FES_RS_LD(23, "v48") \
+    FES_RS_LD(24, "v49") FES_RS_LD(25, "v50") FES_RS_LD(26, "v51") FES_RS_LD(27, "v52") \
+    FES_RS_LD(28, "v53") FES_RS_LD(29, "v54") FES_RS_LD(30, "v55") FES_RS_LD(31, "v56") \
+    FES_RS_LD(32, "v57") FES_RS_LD(33, "v58") FES_RS_LD(34, "v59") FES_RS_LD(35, "v60") \
+    FES_RS_LD(36, "v61") FES_RS_LD(37, "v62") FES_RS_LD(38, "v63") FES_RS_LD(39, "v64") \
+    FES_RS_LD(40, "v65") FES_RS_LD(41, "v66") FES_RS_LD(42, "v67") FES_RS_LD(43, "v68") \
+    FES_RS_LD(44, "v69") FES_RS_LD(45, "v70") FES_RS_LD(46, "v71") FES_RS_LD(47, "v72") \
+    FES_RS_LD(48, "v73") FES_RS_LD(49, "v74") FES_RS_LD(50, "v75") FES_RS_LD(51, "v76") \
+    FES_RS_LD(52, "v77") FES_RS_LD(53, "v78") FES_RS_LD(54, "v79") FES_RS_LD(55, "v80") \
+    FES_RS_LD(56, "v81") FES_RS_LD(57, "v82") FES_RS_LD(58, "v83") FES_RS_LD(59, "v84") \
+    FES_RS_LD(60, "v85") FES_RS_LD(61, "v86") FES_RS_LD(62, "v87") \
+    ""
+#define FES_RS_STORES \
+    FES_RS_ST(0, "v25") FES_RS_ST(1, "v26") FES_RS_ST(2, "v27") FES_RS_ST(3, "v28") \
+    FES_RS_ST(4, "v29") FES_RS_ST(5, "v30") FES_RS_ST(6, "v31") FES_RS_ST(7, "v32") \
+    FES_RS_ST(8, "v33") FES_RS_ST(9, "v34") FES_RS_ST(10, "v35") FES_RS_ST(11, "v36") \
+    FES_RS_ST(12, "v37") FES_RS_ST(13, "v38") FES_RS_ST(14, "v39") FES_RS_ST(15, "v40") \
+    FES_RS_ST(16, "v41") FES_RS_ST(17, "v42") FES_RS_ST(18, "v43") FES_RS_ST(19, "v44") \
+    FES_RS_ST(20, "v45") FES_RS_ST(21, "v46") FES_RS_ST(22, "v47") FES_RS_ST(23, "v48") \
+    FES_RS_ST(24, "v49") FES_RS_ST(25, "v50") FES_RS_ST(26, "v51") FES_RS_ST(27, "v52") \
+    FES_RS_ST(28, "v53") FES_RS_ST(29, "v54") FES_RS_ST(30, "v55") FES_RS_ST(31, "v56") \
+    FES_RS_ST(32, "v57") FES_RS_ST(33, "v58") FES_RS_ST(34, "v59") FES_RS_ST(35, "v60") \
+    FES_RS_ST(36, "v61") FES_RS_ST(37, "v62") FES_RS_ST(38, "v63") FES_RS_ST(39, "v64") \
+    FES_RS_ST(40, "v65") FES_RS_ST(41, "v66") FES_RS_ST(42, "v67") FES_RS_ST(43, "v68") \
+    FES_RS_ST(44, "v69") FES_RS_ST(45, "v70") FES_RS_ST(46, "v71") FES_RS_ST(47, "v72") \
+    FES_RS_ST(48, "v73") FES_RS_ST(49, "v74") FES_RS_ST(50, "v75") FES_RS_ST(51, "v76") \
+    FES_RS_ST(52, "v77") FES_RS_ST(53, "v78") FES_RS_ST(54, "v79") FES_RS_ST(55, "v80") \
+    FES_RS_ST(56, "v81") FES_RS_ST(57, "v82") FES_RS_ST(58, "v83") FES_RS_ST(59, "v84") \
+    FES_RS_ST(60, "v85") FES_RS_ST(61, "v86") FES_RS_ST(62, "v87") \
+    ""
+
 #define FES_RS_PASS_ASM                                                                                   \
     "v_mov_b32 v24, 0\n"                                                                                  \
-    "global_store_dword %[off], v24, %[sig] nt\n"                                                            \
-    "s_cmp_eq_u32 %[n], 0\n"                                                                             \
-    "s_cbranch_scc1 fes_rs_in_done_%=\n"                                                                  \
+    "global_store_dword %[off], v24, %[sig] nt\n"                                                         \
     "s_mov_b64 s[98:99], %[pi]\n"                                                                         \
+    FES_RS_LOADS                                                                                          \
+    "fes_rs_ld_done_%=:\n"                                                                                \
+    "s_waitcnt vmcnt(0)\n"                                                                                \
     "s_add_u32 s92, %[sig_lo], %[wb_lo]\n"                                                                \
     "s_addc_u32 s93, %[sig_hi], %[wb_hi]\n"                                                               \
-    "s_mov_b32 s97, 1\n"                                                                                  \
-    "fes_rs_in_loop_%=:\n"                                                                                \
-    "global_load_dword v16, %[off], s[98:99]\n"                                                           \
-    "s_add_u32 s98, s98, %[wb_lo]\n"                                                                      \
-    "s_addc_u32 s99, s99, %[wb_hi]\n"                                                                     \
-    "s_waitcnt vmcnt(0)\n"                                                                                \
-    "s_set_gpr_idx_on s97, gpr_idx(DST)\n"                                                                \
-    "v_mov_b32 v24, v16\n"                                                                                \
-    "s_set_gpr_idx_off\n"                                                                                 \
-    "global_store_dword %[off], v16, s[92:93] nt\n"                                                          \
-    "s_add_u32 s92, s92, %[wb_lo]\n"                                                                      \
-    "s_addc_u32 s93, s93, %[wb_hi]\n"                                                                     \
-    "s_add_u32 s97, s97, 1\n"                                                                             \
-    "s_cmp_le_u32 s97, %[n]\n"                                                                            \
-    "s_cbranch_scc1 fes_rs_in_loop_%=\n"                                                                  \
-    "fes_rs_in_done_%=:\n"                                                                                \
+    FES_RS_STORES                                                                                         \
+    "fes_rs_st_done_%=:\n"                                                                                \
     "s_mov_b64 s[94:95], %[prog]\n"                                                                       \
     "s_sub_u32 s96, %[nb], 1\n"                                                                           \
     FES_RG_LOAD_A("0x0", "0x40", "0x60")                                                                  \

@@ -415,7 +415,7 @@ std::vector<std::shared_ptr<JitKernel>> jit_kernels(const std::vector<Circuit*>&
     for (size_t i = 0; i < m; ++i) order[i] = i;
     std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cs[a]->uid < cs[b]->uid; });
     std::vector<std::unique_lock<std::mutex>> locks;
-    std::vector<size_t> pending;
+    std::vector<size_t> pending, need_source;
     for (size_t i : order) {
         Circuit& c = *cs[i];
         {
@@ -433,12 +433,17 @@ std::vector<std::shared_ptr<JitKernel>> jit_kernels(const std::vector<Circuit*>&
         for (auto& l : locks) dup |= l.mutex() == &ks[i]->mu;
         if (dup) continue;  // the same circuit twice
         locks.emplace_back(ks[i]->mu);
-        JitKernel& k = *ks[i];
-        if (k.code) continue;
-        k.source = jit_source(c.lut_program(), waves_per_eu, k.block, &k.waves_used);
-        k.hash = fnv1a(k.source);
-        if (!from_cache(k)) pending.push_back(i);
+        if (!ks[i]->code) need_source.push_back(i);
     }
+    // LUT mapping and kernel source of each circuit on host threads in parallel (each kernel
+    // object is locked above and written by one thread), then the code cache, in circuit order.
+    parallel_for(need_source.size(), [&](size_t t) {
+        JitKernel& k = *ks[need_source[t]];
+        k.source = jit_source(cs[need_source[t]]->lut_program(), waves_per_eu, k.block, &k.waves_used);
+        k.hash = fnv1a(k.source);
+    });
+    for (size_t i : need_source)
+        if (!from_cache(*ks[i])) pending.push_back(i);
     // Programs of at most 64 kernels, each under its own entry-point name.
     constexpr size_t kPerProgram = 64;
     for (size_t p0 = 0; p0 < pending.size(); p0 += kPerProgram) {

@@ -1,6 +1,9 @@
 #include "runtime.hpp"
 
 #include <algorithm>
+#include <atomic>
+#include <exception>
+#include <thread>
 #include <chrono>
 #include <cstdarg>
 #include <cstdio>
@@ -304,6 +307,34 @@ Layout layout(size_t k, size_t file_bytes) {
 int max_waves_per_cu(const Device&) { return 32; }
 
 }  // namespace
+
+void parallel_for(size_t n, const std::function<void(size_t)>& f) {
+    if (n == 0) return;
+    const size_t hw = std::max(1u, std::thread::hardware_concurrency());
+    const size_t workers = std::min<size_t>({n, hw, 16});
+    if (workers == 1) {
+        for (size_t i = 0; i < n; ++i) f(i);
+        return;
+    }
+    std::atomic<size_t> next{0};
+    std::mutex emu;
+    std::exception_ptr first;
+    auto run = [&] {
+        for (size_t i; (i = next.fetch_add(1)) < n;) {
+            try {
+                f(i);
+            } catch (...) {
+                std::lock_guard<std::mutex> g(emu);
+                if (!first) first = std::current_exception();
+            }
+        }
+    };
+    std::vector<std::thread> th;
+    for (size_t t = 1; t < workers; ++t) th.emplace_back(run);
+    run();
+    for (auto& t : th) t.join();
+    if (first) std::rethrow_exception(first);
+}
 
 bool regs_tier_enabled() {
     static const bool on = [] {

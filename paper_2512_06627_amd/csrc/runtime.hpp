@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <array>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -156,6 +157,10 @@ hipError_t launch_schedule(const InterpLaunch& L, const Schedule& sch, hipStream
 // tier is switched off (FASTLEC_ES_INTERP_REGS=0).
 bool make_schedule_regs(Device& dev, uint32_t rows, Schedule& out);
 bool regs_tier_enabled();
+// Runs f(0) .. f(n-1) on up to 16 host threads (the caller's included) and returns when all are
+// done; the first exception thrown is rethrown.  For per-circuit host work (LUT mapping, kernel
+// source) over many circuits.
+void parallel_for(size_t n, const std::function<void(size_t)>& f);
 
 struct CheckOut {
     uint64_t best = ~0ull;
