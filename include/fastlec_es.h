@@ -316,7 +316,7 @@ int fastlec_es_submiter_aag(const fastlec_es_circuit *c, const uint32_t *class_o
  *                   (num_instrs - 2 * num_xors); R depends on the value-file size (S)
  *   specialized_ms  t0 + (LUT steps) * max(1, patterns / 2048) / R
  *   compile_ms      hipRTC compile of the specialized kernel: c0 + c1 * (LUT steps)
- * Median errors on the fitting set: 4%, 17%, 0.5%.  Outputs may be NULL; asking for
+ * Median errors on the fitting set: 6%, 15%, 0.7%.  Outputs may be NULL; asking for
  * specialized_ms or compile_ms builds the circuit's LUT program (host time).  The AUTO kernel
  * choice of fastlec_es_check uses the same model. */
 int fastlec_es_predict(const fastlec_es_circuit *c, uint64_t begin_word, uint64_t end_word, double *interp_ms,

@@ -37,7 +37,8 @@ def cones():
             if target * (1 << n) > 3e12:
                 continue
             out.append((f"layered_n{n}_{target}", miters.layered_cone_miter(1000 + n * 7 + target, n, target)))
-    for n, target in ((16, 14000), (16, 20000), (18, 20000), (20, 16000), (22, 12000)):  # files above 232 rows
+    for n, target in ((16, 14000), (16, 20000), (18, 20000), (20, 16000), (22, 12000), (24, 16000),
+                      (26, 20000)):  # files above 232 rows, small and large spaces
         out.append((f"layered_n{n}_{target}", miters.layered_cone_miter(1000 + n * 7 + target, n, target)))
     for name in ("mult6_array_wallace", "mult12_array_booth", "mac8_fused_separate", "mult16_array_booth"):
         out.append((name, miters.workload(name)))

@@ -69,9 +69,13 @@ Schedule autotune(Device& dev, const std::vector<Circuit*>& cs, const std::vecto
         sample_work += per_hw * (double)hw;
     }
     std::vector<Schedule> cands;
+    bool regs_fit = false;
     {
         Schedule rs;
-        if (!hbm && make_schedule_regs(dev, rows_for(cs, 4), rs)) cands.push_back(rs);
+        if (!hbm && make_schedule_regs(dev, rows_for(cs, 4), rs)) {
+            cands.push_back(rs);
+            regs_fit = true;
+        }
     }
     for (int K : {1, 2, 4})
         for (int B : {4, 8, 16})
@@ -80,6 +84,15 @@ Schedule autotune(Device& dev, const std::vector<Circuit*>& cs, const std::vecto
                 Schedule s;
                 if (make_schedule(dev, cs, K, B, block, !hbm, s)) cands.push_back(s);
             }
+    // Files too large for the register tier: device-memory files with one or two words per lane
+    // compete with the LDS candidates (LDS then holds at most two waves per CU).
+    if (!hbm && !regs_fit)
+        for (int K : {1, 2})
+            for (int B : {8, 16})
+                for (int block : {64, 128}) {
+                    Schedule s;
+                    if (make_schedule(dev, cs, K, B, block, false, s)) cands.push_back(s);
+                }
     if (cands.empty()) {
         fastlec_es_options o{};
         o.kernel = hbm ? FASTLEC_KERNEL_INTERP_HBM : FASTLEC_KERNEL_INTERP;

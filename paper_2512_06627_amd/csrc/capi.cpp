@@ -102,7 +102,7 @@ void check_one(Circuit& c, const fastlec_es_options& o, fastlec_es_result* out) 
     Schedule sch;
     if (!spec) {
         std::vector<Circuit*> one{&c};
-        sch = default_schedule(dev, one, &o);
+        sch = default_schedule(dev, one, &o, full.end - full.begin);
         if (o.tile_words) sch.tile_hw = 2ull * o.tile_words;
     }
     // Without a deadline or cancel flag the whole range is one launch.  With one, the range
@@ -395,7 +395,7 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
         for (size_t i : alone) {
             std::vector<Circuit*> one{v[i]};
             std::vector<HwRange> r1{rs[i]};
-            Schedule sch = default_schedule(dev, one, &o);
+            Schedule sch = default_schedule(dev, one, &o, rs[i].end - rs[i].begin);
             if (o.tile_words) sch.tile_hw = 2ull * o.tile_words;
             std::vector<uint64_t> best;
             double ms = 0;

@@ -4,20 +4,20 @@
 
 namespace fes {
 
-// Fitted on one MI355X by least squares on relative error (plain checks of 33 seeded layered cones
+// Fitted on one MI355X by least squares on relative error (plain checks of 35 seeded layered cones
 // and four multiplier and MAC miters, n 12..32; paper_2512_06627_amd/calibrate.py): median (largest)
-// relative error 4% (56%) interpreter, 17% (59%) specialized, 0.5% (4%) compile.  Interpreter gates are
+// relative error 6% (52%) interpreter, 15% (59%) specialized, 0.7% (2%) compile.  Interpreter gates are
 // the instructions of its bundled stream (three-AND XORs count once); its rate depends on the tier
 // that holds the value file.
 namespace model {
-constexpr double kInterpT0Ms = 0.0133;
+constexpr double kInterpT0Ms = 0.0116;
 constexpr uint32_t kTierRows[3] = {104, 144, 232};  // register tier files; LDS or device memory above
-constexpr double kInterpRate[4] = {1.978e14, 2.147e14, 1.938e14, 2.18e13};  // gate instructions*patterns/s
-constexpr double kInterpMsPerGateFloor = 2.00e-5; // one wave pass per gate: spaces below a chip's waves
-constexpr double kSpecT0Ms = 0.0137;
-constexpr double kSpecLutPassesPerS = 6.31e11;
-constexpr double kCompileC0Ms = 103.9;
-constexpr double kCompileMsPerLut = 0.00660;
+constexpr double kInterpRate[4] = {1.958e14, 2.126e14, 1.940e14, 4.04e13};  // gate instructions*patterns/s
+constexpr double kInterpMsPerGateFloor = 2.24e-5; // one wave pass per gate: spaces below a chip's waves
+constexpr double kSpecT0Ms = 0.0135;
+constexpr double kSpecLutPassesPerS = 6.08e11;
+constexpr double kCompileC0Ms = 101.7;
+constexpr double kCompileMsPerLut = 0.00664;
 constexpr double kLutsPerGate = 0.30;
 constexpr double kLutsPerGateLow = 0.20;  // below every cover measured (0.23 layered cones, 0.28 multipliers)
 }  // namespace model

@@ -382,13 +382,23 @@ bool make_schedule_rows(Device& dev, uint32_t rows, int K, int B, int block, boo
         blocks_per_cu = (int)(lds_cu / interp_lds_bytes(rows, K, waves_per_block));
         blocks_per_cu = std::max(1, std::min(blocks_per_cu, max_waves_per_cu(dev) / waves_per_block));
     } else {
-        blocks_per_cu = std::max(1, 16 / waves_per_block);
+        blocks_per_cu = std::max(1, hbm_waves_per_cu() / waves_per_block);
     }
     s.grid = dev.prop.multiProcessorCount * blocks_per_cu;
     return true;
 }
 
-Schedule default_schedule(Device& dev, const std::vector<Circuit*>& cs, const fastlec_es_options* o) {
+int hbm_waves_per_cu() {
+    static const int w = [] {
+        const char* v = std::getenv("FASTLEC_ES_HBM_WAVES");
+        const int x = v ? std::atoi(v) : 0;
+        return x >= 1 && x <= 32 ? x : 8;  // 8 measured best of 8/16/24/32 on files of 268-529 rows
+    }();
+    return w;
+}
+
+Schedule default_schedule(Device& dev, const std::vector<Circuit*>& cs, const fastlec_es_options* o,
+                          uint64_t space_hw) {
     const bool fix_k = o && o->words_per_thread, fix_block = o && o->wg_size;
     const int K0 = fix_k ? (int)o->words_per_thread : 2;
     const int block0 = fix_block ? (int)o->wg_size : 256;
@@ -418,6 +428,15 @@ Schedule default_schedule(Device& dev, const std::vector<Circuit*>& cs, const fa
                     s = t;
                 }
             }
+        // Files too large for the register tier hold at most two waves per CU in LDS (61 KB and
+        // more per wave).  When the space has at least one pass for every wave of a
+        // device-memory launch (one word per lane, one-wave workgroups), that tier is faster
+        // (1.8-3.9x on files of 268-417 rows at 2^22-2^26 half-words); on smaller spaces the
+        // lower latency of LDS wins (1.3-1.5x at 2^11-2^15 half-words).
+        if (have && best < 4 && !fix_k && !fix_block && space_hw) {
+            Schedule h;
+            if (make_schedule(dev, cs, 1, 8, 64, false, h) && space_hw / 64 >= (uint64_t)h.grid) return h;
+        }
         if (have) return s;
     }
     // Value files in device memory.

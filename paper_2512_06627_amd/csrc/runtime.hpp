@@ -157,6 +157,8 @@ hipError_t launch_schedule(const InterpLaunch& L, const Schedule& sch, hipStream
 // tier is switched off (FASTLEC_ES_INTERP_REGS=0).
 bool make_schedule_regs(Device& dev, uint32_t rows, Schedule& out);
 bool regs_tier_enabled();
+// Waves per CU of device-memory-tier launches (FASTLEC_ES_HBM_WAVES, default 8).
+int hbm_waves_per_cu();
 // Runs f(0) .. f(n-1) on up to 16 host threads (the caller's included) and returns when all are
 // done; the first exception thrown is rethrown.  For per-circuit host work (LUT mapping, kernel
 // source) over many circuits.
@@ -207,7 +209,10 @@ void run_interp(Device& dev, const std::vector<Circuit*>& cs, const std::vector<
                 const Schedule& sch, hipStream_t stream, const int* cancel, std::vector<uint64_t>& best,
                 double* kernel_ms, DevMem mem = DevMem{});
 
-Schedule default_schedule(Device& dev, const std::vector<Circuit*>& cs, const fastlec_es_options* o);
+// space_hw: half-words the launch will cover (0 = not known: device-memory files only when
+// neither registers nor LDS hold them).
+Schedule default_schedule(Device& dev, const std::vector<Circuit*>& cs, const fastlec_es_options* o,
+                          uint64_t space_hw = 0);
 // The server's rule: bundles of B, the option's K (default 2) and workgroup (default 256),
 // shrinking the workgroup and then K only until one workgroup's value files fit in LDS.
 Schedule shrink_schedule(Device& dev, const std::vector<Circuit*>& cs, const fastlec_es_options* o, int B);

@@ -268,7 +268,12 @@ void fastlec_es_server::step(const std::vector<Job*>& act) {
         HwRange w{j->cursor, std::min(j->range.end, j->cursor + slice)};
         windows[t] = w;
         step_np += per_hw * (double)(w.end - w.begin);
-        const bool fits = interp_lds_bytes(p.rows, kK, 1) <= lds_blk;
+        // The first group runs in the register tier (or LDS when the caller fixes the schedule);
+        // files too large for registers go to device memory, where more waves per CU fit.
+        int regs_waves = 0;
+        const bool fits = regs_tier_enabled() && !opts.wg_size && !opts.words_per_thread
+                              ? interp_regs_rows(j->c->interp_rows(), &regs_waves) != 0
+                              : interp_lds_bytes(p.rows, kK, 1) <= lds_blk;
         (fits ? lds_c : hbm_c).push_back(j->c);
         (fits ? lds_r : hbm_r).push_back(w);
         (fits ? lds_i : hbm_i).push_back(j->slot);
