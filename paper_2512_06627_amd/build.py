@@ -1,7 +1,8 @@
 """Build the exact-simulation library for gfx950 in-tree (hipcc; no GPU needed).
 
 Produces paper_2512_06627_amd/_lib/libfastlec_es.so from csrc/.  Sources are
-compiled in parallel to objects under _build/, then linked with hipRTC.
+compiled in parallel to objects under _build/, then linked with hipRTC; the compile
+helper program _lib/fastlec_es_rtc is built from rtc/.
 """
 import concurrent.futures
 import os
@@ -51,6 +52,17 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    # The compile helper program (grouped hipRTC compiles in child processes), next to the library.
+    helper = os.path.join(OUT_DIR, "fastlec_es_rtc")
+    cmd = [HIPCC, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-O2", "-std=c++17", "-I/opt/rocm/include",
+           os.path.join(HERE, "rtc", "fastlec_es_rtc.cpp"), "-o", helper + ".tmp",
+           "-L/opt/rocm/lib", "-lhiprtc", "-Wl,-rpath,/opt/rocm/lib"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile helper failed\n{r.stdout}\n{r.stderr}")
+    os.replace(helper + ".tmp", helper)
     return LIB
 
 

@@ -15,13 +15,25 @@
 // The source is compiled once per circuit with hipRTC for gfx950 and cached.
 #include <hip/hiprtc.h>
 
+#include <dlfcn.h>
+#include <spawn.h>
+#include <sys/wait.h>
+#include <unistd.h>
+
 #include <algorithm>
+#include <cerrno>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <iterator>
 #include <sstream>
+#include <thread>
 
+#include "rtc_options.hpp"
 #include "runtime.hpp"
+
+extern char** environ;
 
 namespace fes {
 namespace {
@@ -287,9 +299,7 @@ std::vector<char> compile(const std::string& src, double* ms) {
     const double t0 = now_ms();
     hiprtcProgram prog;
     rtc_check(hiprtcCreateProgram(&prog, src.c_str(), "fes_es_kernel.hip", 0, nullptr, nullptr), "hiprtcCreateProgram");
-    const char* opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
-                          "-packed-fp32-ops"};
-    hiprtcResult r = hiprtcCompileProgram(prog, (int)(sizeof(opts) / sizeof(opts[0])), opts);
+    hiprtcResult r = hiprtcCompileProgram(prog, kRtcOptionCount, const_cast<const char**>(kRtcOptions));
     if (r != HIPRTC_SUCCESS) {
         size_t n = 0;
         hiprtcGetProgramLogSize(prog, &n);
@@ -305,6 +315,88 @@ std::vector<char> compile(const std::string& src, double* ms) {
     hiprtcDestroyProgram(&prog);
     if (ms) *ms = now_ms() - t0;
     return code;
+}
+
+// Compile helper processes (the fastlec_es_rtc program next to this library): hipRTC serializes
+// compiles inside one process, so the programs of a grouped compile run side by side in child
+// processes.  FASTLEC_ES_RTC_PROCS sets how many at once (default: half the host threads, at most
+// 8; 0 compiles in this process).
+std::string helper_path() {
+    static const std::string path = [] {
+        Dl_info info;
+        if (!dladdr((void*)&helper_path, &info) || !info.dli_fname) return std::string();
+        std::string lib = info.dli_fname;
+        const size_t slash = lib.rfind('/');
+        const std::string exe = (slash == std::string::npos ? std::string(".") : lib.substr(0, slash)) + "/fastlec_es_rtc";
+        return access(exe.c_str(), X_OK) == 0 ? exe : std::string();
+    }();
+    return path;
+}
+
+int helper_procs() {
+    static const int n = [] {
+        const char* v = std::getenv("FASTLEC_ES_RTC_PROCS");
+        if (v && *v) return std::max(0, std::min(32, std::atoi(v)));
+        return (int)std::min<unsigned>(8, std::max(1u, std::thread::hardware_concurrency() / 2));
+    }();
+    return helper_path().empty() ? 0 : n;
+}
+
+// Compiles srcs[i] into codes[i] in up to `procs` helper processes at a time; returns false for
+// any program whose helper failed (the caller compiles that one in this process).
+std::vector<uint8_t> compile_in_helpers(const std::vector<std::string>& srcs, std::vector<std::vector<char>>& codes,
+                                        int procs) {
+    std::vector<uint8_t> ok(srcs.size(), 0);
+    const char* tmp = std::getenv("TMPDIR");
+    std::string dir = std::string(tmp && *tmp ? tmp : "/tmp") + "/fes_rtc_XXXXXX";
+    if (!mkdtemp(&dir[0])) return ok;
+    const std::string exe = helper_path();
+    auto file = [&](size_t i, const char* ext) { return dir + "/p" + std::to_string(i) + ext; };
+    // Batches of `procs` helpers; each is waited for by its own pid (never waitpid(-1): children
+    // of the host program are not ours to reap).
+    for (size_t b0 = 0; b0 < srcs.size(); b0 += (size_t)procs) {
+        const size_t b1 = std::min(srcs.size(), b0 + (size_t)procs);
+        std::vector<std::pair<pid_t, size_t>> running;
+        for (size_t i = b0; i < b1; ++i) {
+            std::ofstream(file(i, ".hip"), std::ios::binary) << srcs[i];
+            const std::string a1 = file(i, ".hip"), a2 = file(i, ".co");
+            char* argv[] = {const_cast<char*>(exe.c_str()), const_cast<char*>(a1.c_str()), const_cast<char*>(a2.c_str()),
+                            nullptr};
+            pid_t pid = 0;
+            if (posix_spawn(&pid, exe.c_str(), nullptr, nullptr, argv, environ) == 0) running.push_back({pid, i});
+        }
+        for (auto& r : running) {
+            int status = 0;
+            pid_t w;
+            do {
+                w = waitpid(r.first, &status, 0);
+            } while (w < 0 && errno == EINTR);
+            if (w == r.first && WIFEXITED(status) && WEXITSTATUS(status) == 0) {
+                std::ifstream in(file(r.second, ".co"), std::ios::binary);
+                codes[r.second].assign(std::istreambuf_iterator<char>(in), std::istreambuf_iterator<char>());
+                ok[r.second] = !codes[r.second].empty();
+            }
+        }
+    }
+    for (size_t i = 0; i < srcs.size(); ++i) {
+        std::remove(file(i, ".hip").c_str());
+        std::remove(file(i, ".co").c_str());
+    }
+    rmdir(dir.c_str());
+    return ok;
+}
+
+// Compiles every program; wall-clock milliseconds of the whole set in *ms.
+std::vector<std::vector<char>> compile_programs(const std::vector<std::string>& srcs, double* ms) {
+    const double t0 = now_ms();
+    std::vector<std::vector<char>> codes(srcs.size());
+    std::vector<uint8_t> ok(srcs.size(), 0);
+    const int procs = helper_procs();
+    if (procs > 0 && srcs.size() > 1) ok = compile_in_helpers(srcs, codes, procs);
+    for (size_t i = 0; i < srcs.size(); ++i)
+        if (!ok[i]) codes[i] = compile(srcs[i], nullptr);
+    if (ms) *ms = now_ms() - t0;
+    return codes;
 }
 
 // Process-wide code-object cache keyed by the hash of a kernel's own source (circuits with
@@ -444,37 +536,54 @@ std::vector<std::shared_ptr<JitKernel>> jit_kernels(const std::vector<Circuit*>&
     });
     for (size_t i : need_source)
         if (!from_cache(*ks[i])) pending.push_back(i);
-    // Programs of at most 64 kernels, each under its own entry-point name.
-    constexpr size_t kPerProgram = 64;
-    for (size_t p0 = 0; p0 < pending.size(); p0 += kPerProgram) {
-        const size_t p1 = std::min(pending.size(), p0 + kPerProgram);
+    // Programs of at most 64 kernels, each under its own entry-point name.  With compile helper
+    // processes the kernels are spread over as many programs as run at once, at least 12 each:
+    // every program pays hipRTC's fixed cost (about half of a 12-kernel program's compile), so
+    // smaller groups stay one program (16 kernels: 0.86 s as one program, 0.93 s as two in
+    // parallel; 96 kernels: 5.3 s as two programs in this process, 2.3 s as four helpers, on an
+    // 8-core host).
+    if (pending.empty()) return ks;
+    const size_t procs = (size_t)std::max(1, helper_procs());
+    const size_t programs = std::max<size_t>(1, std::min(procs, pending.size() / 12));
+    size_t per = std::min<size_t>(64, (pending.size() + programs - 1) / programs);
+    std::vector<std::pair<size_t, size_t>> parts;
+    std::vector<std::string> srcs;
+    size_t bytes = 0;
+    for (size_t p0 = 0; p0 < pending.size(); p0 += per) {
+        const size_t p1 = std::min(pending.size(), p0 + per);
         std::string src;
-        size_t bytes = 0;
         for (size_t t = p0; t < p1; ++t) {
             JitKernel& k = *ks[pending[t]];
             k.name = "fes_es_kernel_" + std::to_string(t - p0);
             src += renamed(k.source, k.name);
             bytes += k.source.size();
         }
-        double ms = 0;
-        auto obj = std::make_shared<CodeObject>();
-        try {
-            trace("specialized: compiling %zu kernels in one program (%zu bytes of source)", p1 - p0, bytes);
-            obj->bytes = std::make_shared<const std::vector<char>>(compile(src, &ms));
-        } catch (...) {
-            for (size_t t = p0; t < pending.size(); ++t) {
-                Circuit& c = *cs[pending[t]];
-                std::lock_guard<std::mutex> g(c.mu);
-                c.jit.erase(waves_per_eu);
-            }
-            throw;
+        parts.push_back({p0, p1});
+        srcs.push_back(std::move(src));
+    }
+    double ms = 0;
+    std::vector<std::vector<char>> codes;
+    try {
+        trace("specialized: compiling %zu kernels as %zu programs (%zu bytes of source, %d helper processes)",
+              pending.size(), srcs.size(), bytes, helper_procs());
+        codes = compile_programs(srcs, &ms);
+    } catch (...) {
+        for (size_t t = 0; t < pending.size(); ++t) {
+            Circuit& c = *cs[pending[t]];
+            std::lock_guard<std::mutex> g(c.mu);
+            c.jit.erase(waves_per_eu);
         }
-        trace("specialized: compiled %zu kernels in %.0f ms", p1 - p0, ms);
-        std::lock_guard<std::mutex> cg(g_cache_mu);
-        for (size_t t = p0; t < p1; ++t) {
+        throw;
+    }
+    trace("specialized: compiled %zu kernels in %.0f ms", pending.size(), ms);
+    std::lock_guard<std::mutex> cg(g_cache_mu);
+    for (size_t q = 0; q < parts.size(); ++q) {
+        auto obj = std::make_shared<CodeObject>();
+        obj->bytes = std::make_shared<const std::vector<char>>(std::move(codes[q]));
+        for (size_t t = parts[q].first; t < parts[q].second; ++t) {
             JitKernel& k = *ks[pending[t]];
             k.code = obj;
-            k.compile_ms = ms / (double)(p1 - p0);
+            k.compile_ms = ms / (double)pending.size();
             if (compile_ms) (*compile_ms)[pending[t]] = k.compile_ms;
             code_cache()[k.hash] = {obj->bytes, k.name};
         }
