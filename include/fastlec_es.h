@@ -142,7 +142,8 @@ int fastlec_es_check(const fastlec_es_circuit *c, const fastlec_es_options *opts
  * interpreter instead.  With kernel SPECIALIZED every circuit runs on its specialized kernel
  * that way.  Of the others, those predicted to take at least 1 ms on the interpreter run as
  * their own launches with their own schedule (unless the options fix words_per_thread or
- * wg_size); the rest are grouped by value-file size (powers of two of the row count); each group
+ * wg_size); the rest are grouped by value-file size (the register tier's 104, 144 and 232 rows,
+ * above that powers of two of the row count); each group
  * is one persistent interpreter launch over all its cones, in longest-processing-time order by
  * the runtime model's time, with a tuned schedule (or the option's schedule fields) and recorded
  * once as a hipGraph; their kernel_ms is the sum over the groups.  cs: k handles; out: k
@@ -353,11 +354,15 @@ int fastlec_es_valu_probe(int device, uint32_t variant, uint32_t waves_per_simd,
 int fastlec_es_compile_specialized(const fastlec_es_circuit *c, int waves_per_eu, double *compile_ms,
                                    size_t *code_bytes);
 
-/* Compile the specialized kernels of k circuits together, as few hipRTC programs as possible
- * (up to 64 kernels each, every kernel under its own entry point), without running them; no GPU
- * needed.  Kernels already compiled or cached are reused.  hipRTC's fixed cost (about 0.1 s per
- * program) is paid once per program instead of once per circuit.  *compile_ms (may be NULL) =
- * total compile time paid by this call.  Later checks of these circuits use the kernels. */
+/* Compile the specialized kernels of k circuits together as hipRTC programs of up to 64 kernels
+ * each (every kernel under its own entry point), without running them; no GPU needed.  Kernels
+ * already compiled or cached are reused.  hipRTC's fixed cost (about 0.1 s per program) is paid
+ * once per program instead of once per circuit.  With at least 24 kernels to compile they are
+ * split into several programs of at least 12 kernels, compiled FASTLEC_ES_RTC_PROCS at a time
+ * (default min(8, half the host threads)) by child processes running the helper program
+ * fastlec_es_rtc, which sits beside the library; a program whose helper fails or is missing is
+ * compiled in this process.  *compile_ms (may be NULL) = total compile time paid by this call.  Later checks of
+ * these circuits use the kernels. */
 int fastlec_es_compile_specialized_many(const fastlec_es_circuit *const *cs, size_t k, int waves_per_eu,
                                         double *compile_ms);
 
