@@ -354,9 +354,9 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (HBM counter calibration)")
-    ap.add_argument("--leg", choices=["rsim", "sweep", "valu_peak", "interp", "batch"], default=None,
-                    help="run only this leg (random simulation, a sweeping pass or the VALU issue-rate "
-                         "probe) and print its JSON")
+    ap.add_argument("--leg", choices=["rsim", "sweep", "valu_peak", "interp", "batch", "serve"], default=None,
+                    help="run only this leg (random simulation, a sweeping pass, the VALU issue-rate "
+                         "probe, the interpreter, batch or serving workload) and print its JSON")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only: exact simulation here is a single-GPU build "
@@ -379,7 +379,8 @@ def main():
         if a.leg == "valu_peak":
             print(json.dumps({"leg": a.leg, **valu_peak(es)}), flush=True)
             return
-        leg = {"rsim": rsim_leg, "sweep": sweep_leg, "interp": interp_leg, "batch": batch_leg}[a.leg]
+        leg = {"rsim": rsim_leg, "sweep": sweep_leg, "interp": interp_leg, "batch": batch_leg,
+               "serve": lambda e, s: serve_leg(e, s, seconds=a.serve_seconds)}[a.leg]
         print(json.dumps({"leg": a.leg, **leg(es, stream)}), flush=True)
         return
     g = miters.workload(a.workload)

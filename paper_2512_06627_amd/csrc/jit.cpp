@@ -386,15 +386,23 @@ std::vector<uint8_t> compile_in_helpers(const std::vector<std::string>& srcs, st
     return ok;
 }
 
-// Compiles every program; wall-clock milliseconds of the whole set in *ms.
-std::vector<std::vector<char>> compile_programs(const std::vector<std::string>& srcs, double* ms) {
+// Compiles every program; wall-clock milliseconds of the whole set in *ms.  Several programs
+// compile in helper processes side by side; a lone program compiles in this process unless
+// `alone_in_helper` (a caller that runs several compiles at once: compiles in this process
+// would serialize).
+std::vector<std::vector<char>> compile_programs(const std::vector<std::string>& srcs, double* ms,
+                                                bool alone_in_helper) {
     const double t0 = now_ms();
     std::vector<std::vector<char>> codes(srcs.size());
     std::vector<uint8_t> ok(srcs.size(), 0);
     const int procs = helper_procs();
-    if (procs > 0 && srcs.size() > 1) ok = compile_in_helpers(srcs, codes, procs);
+    if (procs > 0 && (srcs.size() > 1 || alone_in_helper)) ok = compile_in_helpers(srcs, codes, procs);
     for (size_t i = 0; i < srcs.size(); ++i)
-        if (!ok[i]) codes[i] = compile(srcs[i], nullptr);
+        if (!ok[i]) {
+            if (procs > 0 && (srcs.size() > 1 || alone_in_helper))
+                trace("specialized: helper failed on program %zu; compiling it in this process", i);
+            codes[i] = compile(srcs[i], nullptr);
+        }
     if (ms) *ms = now_ms() - t0;
     return codes;
 }
@@ -496,8 +504,10 @@ std::shared_ptr<JitKernel> jit_kernel(Circuit& c, int waves_per_eu, double* comp
     return k;
 }
 
+int compile_helpers() { return helper_procs(); }
+
 std::vector<std::shared_ptr<JitKernel>> jit_kernels(const std::vector<Circuit*>& cs, int waves_per_eu,
-                                                    std::vector<double>* compile_ms) {
+                                                    std::vector<double>* compile_ms, CompileSplit split) {
     const size_t m = cs.size();
     std::vector<std::shared_ptr<JitKernel>> ks(m);
     if (compile_ms) compile_ms->assign(m, 0.0);
@@ -537,14 +547,16 @@ std::vector<std::shared_ptr<JitKernel>> jit_kernels(const std::vector<Circuit*>&
     for (size_t i : need_source)
         if (!from_cache(*ks[i])) pending.push_back(i);
     // Programs of at most 64 kernels, each under its own entry-point name.  With compile helper
-    // processes the kernels are spread over as many programs as run at once, at least 12 each:
-    // every program pays hipRTC's fixed cost (about half of a 12-kernel program's compile), so
-    // smaller groups stay one program (16 kernels: 0.86 s as one program, 0.93 s as two in
-    // parallel; 96 kernels: 5.3 s as two programs in this process, 2.3 s as four helpers, on an
-    // 8-core host).
+    // processes a group of 4 or more kernels is spread over as many programs as run at once
+    // (every program pays hipRTC's fixed cost, but they overlap; on a 16-core host 16 kernels
+    // took 0.34-0.39 s as one program and 0.16-0.17 s as eight, 4 kernels 0.18-0.19 s against
+    // 0.14-0.15 s); fewer stay one program in this process, which saves a helper's start-up.
+    // CompileSplit::kEach gives every kernel a program of its own, in a helper even when alone.
     if (pending.empty()) return ks;
     const size_t procs = (size_t)std::max(1, helper_procs());
-    const size_t programs = std::max<size_t>(1, std::min(procs, pending.size() / 12));
+    const bool each = split == CompileSplit::kEach;
+    const size_t programs =
+        each ? pending.size() : pending.size() >= 4 ? std::min(procs, pending.size()) : 1;
     size_t per = std::min<size_t>(64, (pending.size() + programs - 1) / programs);
     std::vector<std::pair<size_t, size_t>> parts;
     std::vector<std::string> srcs;
@@ -566,7 +578,7 @@ std::vector<std::shared_ptr<JitKernel>> jit_kernels(const std::vector<Circuit*>&
     try {
         trace("specialized: compiling %zu kernels as %zu programs (%zu bytes of source, %d helper processes)",
               pending.size(), srcs.size(), bytes, helper_procs());
-        codes = compile_programs(srcs, &ms);
+        codes = compile_programs(srcs, &ms, each);
     } catch (...) {
         for (size_t t = 0; t < pending.size(); ++t) {
             Circuit& c = *cs[pending[t]];

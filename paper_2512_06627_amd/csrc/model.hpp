@@ -40,8 +40,7 @@ double lpt_cost_ms(uint32_t interp_gates, uint32_t rows, double patterns);
 // predicted time alone.  Its specialized kernel is compiled (on a background thread, while the
 // job keeps running on the interpreter) when that remaining time exceeds the predicted
 // specialized time of the same work plus twice the predicted compile time: the factor is the
-// paper's largest safety margin, and it also covers the wait behind other jobs' compiles on the
-// one compile thread.
+// paper's largest safety margin, and it also covers the wait behind other jobs' compiles.
 struct TierJob {
     uint32_t interp_gates = 1;  // bundled-stream gate instructions
     uint32_t rows = 0;          // value-file rows of the interpreter's stream (its tier)

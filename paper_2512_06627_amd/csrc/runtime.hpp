@@ -252,12 +252,23 @@ int specialized_waves_per_eu();
 int specialized_block();
 int specialized_scalar_policy();  // FASTLEC_ES_JIT_SCALAR: 0 all, 1 pure uniform only, 2 none
 std::shared_ptr<JitKernel> jit_kernel(Circuit& c, int waves_per_eu, double* compile_ms);
-// The specialized kernels of several circuits, compiled as few hipRTC programs (each kernel
-// under its own name): hipRTC's fixed cost, about 0.1 s per program, is paid once per program
-// instead of once per circuit.  Kernels already compiled or cached are reused.  compile_ms (if
-// not null) receives each circuit's share of the compile time (0 for reused kernels).
+// How jit_kernels splits kernels into hipRTC programs.  kGroup: a group of 4 or more kernels
+// is spread over the compile helper processes (as many programs as helpers run at once), fewer
+// form one program compiled in this process.  kEach: every kernel is a program of its own,
+// compiled in a helper process even when alone, so that several callers' compiles overlap.
+enum class CompileSplit { kGroup, kEach };
+// Number of compile helper processes run at once (FASTLEC_ES_RTC_PROCS, default min(8, half the
+// host threads)); 0 when the helper program is missing: compiles then run in this process, and
+// hipRTC serializes them.
+int compile_helpers();
+// The specialized kernels of several circuits, compiled as hipRTC programs of one or more
+// kernels (each under its own name): hipRTC's fixed cost, about 0.1 s per program, is paid once
+// per program instead of once per circuit, and programs compile side by side in helper
+// processes.  Kernels already compiled or cached are reused.  compile_ms (if not null) receives
+// each circuit's share of the compile time (0 for reused kernels).
 std::vector<std::shared_ptr<JitKernel>> jit_kernels(const std::vector<Circuit*>& cs, int waves_per_eu,
-                                                    std::vector<double>* compile_ms);
+                                                    std::vector<double>* compile_ms,
+                                                    CompileSplit split = CompileSplit::kGroup);
 // The circuit's specialized kernel if it is already compiled, else null.  Never compiles and
 // never waits: a kernel whose compile is in progress counts as not ready.
 std::shared_ptr<JitKernel> jit_ready(Circuit& c, int waves_per_eu);

@@ -17,9 +17,10 @@
 //
 // Specialized tier: pattern spaces differ by many orders of magnitude (2^n), so a
 // few large jobs carry most of the work.  A job whose remaining interpreter time is
-// estimated well above the cost of compiling its specialized kernel is handed to a
-// compile thread while it keeps running on the interpreter; from the step after the
-// kernel is ready, the job's slices run on the specialized kernel instead (same
+// estimated well above the cost of compiling its specialized kernel is handed to the
+// compile threads (one per compile helper process) while it keeps running on the
+// interpreter; from the step after the kernel is ready, the job's slices run on the
+// specialized kernel instead (same
 // ascending slices, same best[] entry, so the answer cannot change).  Circuits
 // submitted again reuse their compiled kernel at once.
 #include <algorithm>
@@ -48,8 +49,8 @@ struct Job {
     bool done = false;
     int status = FASTLEC_OK;
     fastlec_es_result res{};
-    bool compile_queued = false;     // handed to the compile thread
-    bool compiling = false;          // the compile thread is using the circuit
+    bool compile_queued = false;     // handed to the compile threads
+    bool compiling = false;          // a compile thread is using the circuit
     std::shared_ptr<JitKernel> jit;  // set when the specialized kernel is ready
 };
 
@@ -110,7 +111,7 @@ struct fastlec_es_server {
     size_t off_ctl_jit = 0;  // per-slot claim counters of specialized launches
     std::deque<Job*> compile_queue;
     std::condition_variable cv_compile;
-    std::thread compiler;
+    std::vector<std::thread> compilers;
     void compile_loop();
     void plan_tiers(const std::vector<Job*>& act);
 
@@ -125,9 +126,13 @@ struct fastlec_es_server {
 };
 
 void fastlec_es_server::compile_loop() {
-    // Up to this many queued jobs compile as one hipRTC program: its fixed cost (about 0.1 s)
-    // is then paid once for the group.
-    constexpr size_t kGroup = 8;
+    // With compile helper processes there is one compile thread per helper, and each takes one
+    // job at a time: its kernel compiles alone in a helper as soon as a thread is free, so a
+    // job never waits for the rest of a group (the threads' compiles overlap; in this process
+    // they would serialize).  Without helpers one thread takes up to eight queued jobs and
+    // compiles their kernels as one program, paying hipRTC's fixed cost (about 0.1 s) once.
+    const bool helpers = compile_helpers() > 0;
+    const size_t kGroup = helpers ? 1 : 8;
     for (;;) {
         std::vector<Job*> group;
         {
@@ -160,7 +165,8 @@ void fastlec_es_server::compile_loop() {
         for (Job* j : group) cs.push_back(j->c);
         std::vector<std::shared_ptr<JitKernel>> ks;
         try {
-            ks = jit_kernels(cs, specialized_waves_per_eu(), nullptr);
+            ks = jit_kernels(cs, specialized_waves_per_eu(), nullptr,
+                             helpers ? CompileSplit::kEach : CompileSplit::kGroup);
         } catch (...) {
             // one kernel that does not compile must not keep the others on the interpreter
             ks.assign(group.size(), nullptr);
@@ -233,7 +239,7 @@ void fastlec_es_server::step(const std::vector<Job*>& act) {
     const int kK = server_k(), kB = server_bundle();
     // Slices: equal gate-evaluation budget per job, at least 16 passes.
     const uint32_t pass_hw = 64u * kK;
-    // Tier of every job for this step (the compile thread may set a kernel meanwhile).
+    // Tier of every job for this step (a compile thread may set a kernel meanwhile).
     std::vector<std::shared_ptr<JitKernel>> jk(act.size());
     {
         std::lock_guard<std::mutex> g(mu);
@@ -534,7 +540,8 @@ int fastlec_es_server_create(const fastlec_es_options* opts, size_t budget_bytes
         s->st.budget_bytes = budget_bytes;
         fastlec_es_server* raw = s.get();
         s->th = std::thread([raw] { raw->loop(); });
-        s->compiler = std::thread([raw] { raw->compile_loop(); });
+        for (int t = 0, n = std::max(1, compile_helpers()); t < n; ++t)
+            s->compilers.emplace_back([raw] { raw->compile_loop(); });
         *out = s.release();
         return FASTLEC_OK;
     } catch (const Error& e) {
@@ -603,7 +610,8 @@ void fastlec_es_server_destroy(fastlec_es_server* s) {
     s->cv_work.notify_all();
     s->cv_compile.notify_all();
     if (s->th.joinable()) s->th.join();
-    if (s->compiler.joinable()) s->compiler.join();
+    for (auto& t : s->compilers)
+        if (t.joinable()) t.join();
     if (s->table.dev) s->dev->release(s->table);
     if (s->files.dev) (void)hipFree(s->files.dev);
     delete s;

@@ -271,8 +271,11 @@ std::shared_ptr<JitKernel> jit_kernel(Circuit& c, int waves_per_eu, double* comp
     if (compile_ms) *compile_ms = 3.0;
     return fake_compile(c, waves_per_eu);
 }
+// Three compile threads in the server, as with helper processes.
+int compile_helpers() { return 3; }
+
 std::vector<std::shared_ptr<JitKernel>> jit_kernels(const std::vector<Circuit*>& cs, int waves_per_eu,
-                                                    std::vector<double>* compile_ms) {
+                                                    std::vector<double>* compile_ms, CompileSplit) {
     std::vector<std::shared_ptr<JitKernel>> out;
     for (Circuit* c : cs) out.push_back(fake_compile(*c, waves_per_eu));
     if (compile_ms) compile_ms->assign(cs.size(), 3.0);

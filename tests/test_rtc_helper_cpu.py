@@ -2,9 +2,12 @@
 compiles run in child processes side by side, since hipRTC serializes compiles inside one process.
 hipRTC needs no GPU, so this runs on the CPU: the helper produces the same code object as the
 library's in-process compile, reports a failing source with a non-zero status and hipRTC's log,
-and a grouped compile of 24 kernels is split into two programs compiled by helpers (one program
-in this process when helpers are turned off)."""
+a grouped compile of 24 kernels is split into one program per helper (one program in this process
+when helpers are turned off), fewer than 4 kernels stay one program, and programs whose helper
+fails are compiled in this process.  comgr's on-disk compile cache is turned off in the child
+processes, so every compile is a real one."""
 import os
+import shutil
 import subprocess
 import sys
 
@@ -37,15 +40,34 @@ def test_helper_reports_a_failing_source(tmp_path):
     assert not (tmp_path / "bad.co").exists()
 
 
-@pytest.mark.parametrize("procs,programs", [("4", 2), ("0", 1)])
-def test_grouped_compile_in_helper_processes(procs, programs):
+def _grouped_compile(k, procs, seed, lib_path=None):
     code = ("import sys; sys.path.insert(0, %r)\n"
             "import miters, paper_2512_06627_amd as es\n"
-            "cs = [es.fastlec_es_load_aig(miters.layered_cone_miter(7400 + i, 18, 900).to_aig()) for i in range(24)]\n"
+            "if %r: es.LIB_PATH = %r\n"
+            "cs = [es.fastlec_es_load_aig(miters.layered_cone_miter(%d + i, 18, 900).to_aig()) for i in range(%d)]\n"
             "es.fastlec_es_compile_specialized_many(cs, 3)\n"
-            "print('compiled', all(es.fastlec_es_compile_specialized(c, 3)['compile_ms'] == 0 for c in cs))\n" % ROOT)
-    env = dict(os.environ, FASTLEC_ES_RTC_PROCS=procs, FASTLEC_ES_TRACE="1")
+            "print('compiled', all(es.fastlec_es_compile_specialized(c, 3)['compile_ms'] == 0 for c in cs))\n"
+            % (ROOT, bool(lib_path), lib_path, seed, k))
+    env = dict(os.environ, FASTLEC_ES_RTC_PROCS=procs, FASTLEC_ES_TRACE="1", AMD_COMGR_CACHE="0")
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=600, env=env)
     assert r.returncode == 0, r.stderr[-3000:]
     assert "compiled True" in r.stdout, r.stdout  # every kernel cached after the grouped compile
-    assert f"compiling 24 kernels as {programs} programs" in r.stderr, r.stderr[-3000:]
+    return r.stderr
+
+
+@pytest.mark.parametrize("k,procs,programs", [(24, "4", 4), (24, "0", 1), (3, "4", 1)])
+def test_grouped_compile_in_helper_processes(k, procs, programs):
+    err = _grouped_compile(k, procs, 7400)
+    assert f"compiling {k} kernels as {programs} programs" in err, err[-3000:]
+
+
+def test_failing_helper_falls_back_to_in_process_compile(tmp_path):
+    # A copy of the library whose neighbouring helper always fails: every program is then
+    # compiled in the process, and every kernel is still there.
+    shutil.copy(es.LIB_PATH, tmp_path / os.path.basename(es.LIB_PATH))
+    helper = tmp_path / "fastlec_es_rtc"
+    helper.write_text("#!/bin/sh\nexit 3\n")
+    helper.chmod(0o755)
+    err = _grouped_compile(6, "3", 7500, str(tmp_path / os.path.basename(es.LIB_PATH)))
+    assert "compiling 6 kernels as 3 programs" in err, err[-3000:]
+    assert err.count("helper failed on program") == 3, err[-3000:]
