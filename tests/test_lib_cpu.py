@@ -180,17 +180,16 @@ def test_runtime_model_properties():
 
 
 def test_specialized_kernels_compile_together():
-    """Several circuits' kernels in one hipRTC program: one fixed cost, each kernel reachable
-    afterwards (a single compile of each circuit then costs nothing and reports the shared
-    code object), and one call with a repeated circuit compiles it once."""
+    """Several circuits' kernels compiled in one call: each kernel reachable afterwards (a
+    single compile of each circuit then costs nothing and reports its code object), and one
+    call with a repeated circuit compiles it once.  How the kernels are split into programs
+    (one program, or one per compile helper process) is pinned in test_rtc_helper_cpu.py."""
     cs = [es.fastlec_es_load_aig(miters.layered_cone_miter(800 + i, 25, 1200).to_aig()) for i in range(6)]
     assert es.fastlec_es_compile_specialized_many(cs + cs[:2], 3) > 0
-    sizes = set()
     for c in cs:
         r = es.fastlec_es_compile_specialized(c, 3)
         assert r["compile_ms"] == 0
-        sizes.add(r["code_bytes"])
-    assert len(sizes) == 1  # one code object holds all six kernels
+        assert r["code_bytes"] > 0
     assert es.fastlec_es_compile_specialized_many(cs, 3) == 0
     with pytest.raises(es.EsError):
         es.fastlec_es_compile_specialized_many(cs, 0)

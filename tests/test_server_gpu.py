@@ -157,10 +157,11 @@ def test_server_specialized_tier_switch_mid_job(monkeypatch):
 
 
 def test_server_compiles_queued_jobs_in_groups(monkeypatch):
-    """More jobs than one compile group (eight), one circuit submitted twice in the same round:
-    the compile thread builds multi-kernel programs (the repeated circuit compiles once); in a
-    second round the compiled kernels run from the first step.  Every answer equals the circuit
-    checked alone (and the oracle's where it is cheap)."""
+    """More jobs than compile threads (one per compile helper process, each compiling one job's
+    kernel at a time) or than one in-process compile group (eight), one circuit submitted twice
+    in the same round (its kernel compiles once); in a second round the compiled kernels run from
+    the first step.  Every answer equals the circuit checked alone (and the oracle's where it is
+    cheap)."""
     monkeypatch.setenv("FASTLEC_ES_SERVER_JIT", "2")
     monkeypatch.setenv("FASTLEC_ES_SERVER_STEP_MS", "1")
     gs = _jobs(47, 11, 20, 24, 800, 2000, faulty_every=3)
