@@ -22,11 +22,15 @@
 
 #include <algorithm>
 #include <cerrno>
+#include <chrono>
+#include <condition_variable>
+#include <csignal>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <iterator>
+#include <mutex>
 #include <sstream>
 #include <thread>
 
@@ -342,8 +346,29 @@ int helper_procs() {
     return helper_path().empty() ? 0 : n;
 }
 
-// Compiles srcs[i] into codes[i] in up to `procs` helper processes at a time; returns false for
-// any program whose helper failed (the caller compiles that one in this process).
+// Helper processes running at once in this process, over all callers (the server's compile
+// threads and batch calls share the limit helper_procs()).
+std::mutex g_helper_mu;
+std::condition_variable g_helper_cv;
+int g_helpers_running = 0;
+
+// Seconds a helper may run before it is killed and its program compiled in this process
+// (FASTLEC_ES_RTC_TIMEOUT_S, default 300).
+double helper_timeout_s() {
+    static const double t = [] {
+        const char* v = std::getenv("FASTLEC_ES_RTC_TIMEOUT_S");
+        const double x = v && *v ? std::atof(v) : 0.0;
+        return x > 0 ? x : 300.0;
+    }();
+    return t;
+}
+
+// Compiles srcs[i] into codes[i] in helper processes, at most `procs` of them running at once
+// in the whole process; returns false for any program whose helper failed, timed out or could
+// not start (the caller compiles that one in this process).  The helper writes its code object
+// under a temporary name and renames it when complete, so a code object that exists is whole.
+// Children start with only stdin, stdout and stderr open: they hold none of the host program's
+// files (GPU device nodes included).
 std::vector<uint8_t> compile_in_helpers(const std::vector<std::string>& srcs, std::vector<std::vector<char>>& codes,
                                         int procs) {
     std::vector<uint8_t> ok(srcs.size(), 0);
@@ -352,35 +377,88 @@ std::vector<uint8_t> compile_in_helpers(const std::vector<std::string>& srcs, st
     if (!mkdtemp(&dir[0])) return ok;
     const std::string exe = helper_path();
     auto file = [&](size_t i, const char* ext) { return dir + "/p" + std::to_string(i) + ext; };
-    // Batches of `procs` helpers; each is waited for by its own pid (never waitpid(-1): children
-    // of the host program are not ours to reap).
-    for (size_t b0 = 0; b0 < srcs.size(); b0 += (size_t)procs) {
-        const size_t b1 = std::min(srcs.size(), b0 + (size_t)procs);
-        std::vector<std::pair<pid_t, size_t>> running;
-        for (size_t i = b0; i < b1; ++i) {
+    posix_spawn_file_actions_t fa;
+    posix_spawn_file_actions_init(&fa);
+    posix_spawn_file_actions_addclosefrom_np(&fa, 3);
+    struct Child {
+        pid_t pid;
+        size_t i;
+        double deadline;
+    };
+    std::vector<Child> running;
+    size_t next = 0;
+    auto collect = [&](const Child& c, bool exited_ok) {
+        if (exited_ok) {
+            std::ifstream in(file(c.i, ".co"), std::ios::binary);
+            if (in) codes[c.i].assign(std::istreambuf_iterator<char>(in), std::istreambuf_iterator<char>());
+            ok[c.i] = !codes[c.i].empty();
+        }
+        std::lock_guard<std::mutex> g(g_helper_mu);
+        --g_helpers_running;
+        g_helper_cv.notify_all();
+    };
+    while (next < srcs.size() || !running.empty()) {
+        // Start helpers while the process-wide limit allows; wait for a slot only when none of
+        // this call's helpers is running (their completion frees slots too).
+        while (next < srcs.size()) {
+            {
+                std::unique_lock<std::mutex> g(g_helper_mu);
+                if (running.empty())
+                    g_helper_cv.wait(g, [&] { return g_helpers_running < procs; });
+                if (g_helpers_running >= procs) break;
+                ++g_helpers_running;
+            }
+            const size_t i = next++;
             std::ofstream(file(i, ".hip"), std::ios::binary) << srcs[i];
             const std::string a1 = file(i, ".hip"), a2 = file(i, ".co");
             char* argv[] = {const_cast<char*>(exe.c_str()), const_cast<char*>(a1.c_str()), const_cast<char*>(a2.c_str()),
                             nullptr};
             pid_t pid = 0;
-            if (posix_spawn(&pid, exe.c_str(), nullptr, nullptr, argv, environ) == 0) running.push_back({pid, i});
-        }
-        for (auto& r : running) {
-            int status = 0;
-            pid_t w;
-            do {
-                w = waitpid(r.first, &status, 0);
-            } while (w < 0 && errno == EINTR);
-            if (w == r.first && WIFEXITED(status) && WEXITSTATUS(status) == 0) {
-                std::ifstream in(file(r.second, ".co"), std::ios::binary);
-                codes[r.second].assign(std::istreambuf_iterator<char>(in), std::istreambuf_iterator<char>());
-                ok[r.second] = !codes[r.second].empty();
+            if (posix_spawn(&pid, exe.c_str(), &fa, nullptr, argv, environ) == 0) {
+                running.push_back({pid, i, now_ms() + 1000.0 * helper_timeout_s()});
+            } else {
+                std::lock_guard<std::mutex> g(g_helper_mu);
+                --g_helpers_running;
+                g_helper_cv.notify_all();
             }
         }
+        // Reap this call's helpers by their own pids (never waitpid(-1): children of the host
+        // program are not ours to reap).
+        bool progressed = false;
+        for (size_t r = 0; r < running.size();) {
+            int status = 0;
+            const pid_t w = waitpid(running[r].pid, &status, WNOHANG);
+            bool done = false, good = false;
+            if (w == running[r].pid) {
+                done = true;
+                good = WIFEXITED(status) && WEXITSTATUS(status) == 0;
+            } else if (w < 0 && errno != EINTR) {
+                // Reaped elsewhere (a host program that ignores SIGCHLD): the renamed code object
+                // tells whether the helper finished.
+                done = true;
+                good = access(file(running[r].i, ".co").c_str(), R_OK) == 0;
+            } else if (w == 0 && now_ms() > running[r].deadline) {
+                trace("specialized: helper for program %zu timed out; killing it", running[r].i);
+                kill(running[r].pid, SIGKILL);
+                while (waitpid(running[r].pid, &status, 0) < 0 && errno == EINTR) {
+                }
+                done = true;
+            }
+            if (done) {
+                collect(running[r], good);
+                running.erase(running.begin() + (long)r);
+                progressed = true;
+            } else {
+                ++r;
+            }
+        }
+        if (!progressed && !running.empty()) std::this_thread::sleep_for(std::chrono::milliseconds(1));
     }
+    posix_spawn_file_actions_destroy(&fa);
     for (size_t i = 0; i < srcs.size(); ++i) {
         std::remove(file(i, ".hip").c_str());
         std::remove(file(i, ".co").c_str());
+        std::remove((file(i, ".co") + ".part").c_str());
     }
     rmdir(dir.c_str());
     return ok;

@@ -6,6 +6,8 @@
 //
 // Usage: fastlec_es_rtc <source file> <code object file>
 // Exit status 0 with the code object written; otherwise non-zero with hipRTC's log on stderr.
+// The code object is written to "<code object file>.part" and renamed when complete, so the
+// file under its own name is always whole.
 #include <hip/hiprtc.h>
 
 #include <cstdio>
@@ -46,10 +48,20 @@ int main(int argc, char** argv) {
     std::vector<char> code(size);
     hiprtcGetCode(prog, code.data());
     hiprtcDestroyProgram(&prog);
-    std::ofstream out(argv[2], std::ios::binary);
-    out.write(code.data(), (std::streamsize)code.size());
-    if (!out) {
-        std::fprintf(stderr, "fastlec_es_rtc: cannot write %s\n", argv[2]);
+    const std::string part = std::string(argv[2]) + ".part";
+    {
+        std::ofstream out(part, std::ios::binary);
+        out.write(code.data(), (std::streamsize)code.size());
+        out.close();
+        if (!out) {
+            std::fprintf(stderr, "fastlec_es_rtc: cannot write %s\n", part.c_str());
+            std::remove(part.c_str());
+            return 1;
+        }
+    }
+    if (std::rename(part.c_str(), argv[2]) != 0) {
+        std::fprintf(stderr, "fastlec_es_rtc: cannot rename %s\n", part.c_str());
+        std::remove(part.c_str());
         return 1;
     }
     return 0;
