@@ -360,8 +360,9 @@ int fastlec_es_compile_specialized(const fastlec_es_circuit *c, int waves_per_eu
  * once per program instead of once per circuit.  With at least 24 kernels to compile they are
  * split into several programs of at least 12 kernels, compiled FASTLEC_ES_RTC_PROCS at a time
  * (default min(8, half the host threads)) by child processes running the helper program
- * fastlec_es_rtc, which sits beside the library; a program whose helper fails or is missing is
- * compiled in this process.  *compile_ms (may be NULL) = total compile time paid by this call.  Later checks of
+ * fastlec_es_rtc, which sits beside the library; a program whose helper fails, is missing or runs
+ * longer than FASTLEC_ES_RTC_TIMEOUT_S seconds (300) is compiled in this process.  Helpers start
+ * with only stdin, stdout and stderr open and are always waited for before the call returns.  *compile_ms (may be NULL) = total compile time paid by this call.  Later checks of
  * these circuits use the kernels. */
 int fastlec_es_compile_specialized_many(const fastlec_es_circuit *const *cs, size_t k, int waves_per_eu,
                                         double *compile_ms);
