@@ -147,8 +147,10 @@ int fastlec_es_check(const fastlec_es_circuit *c, const fastlec_es_options *opts
  * is one persistent interpreter launch over all its cones, in longest-processing-time order by
  * the runtime model's time, with a tuned schedule (or the option's schedule fields) and recorded
  * once as a hipGraph; their kernel_ms is the sum over the groups.  cs: k handles; out: k
- * results.  An error (a null handle, a device or runtime failure) fails the whole call with its
- * status; the out entries are then not valid. */
+ * results.  An entry's own error (a null handle) is reported in that entry: its verdict is the
+ * negative status (FASTLEC_ERR_INVALID) and its other fields are zero; the other entries are
+ * checked and valid, and the call returns the first entry's status.  A device or runtime failure
+ * fails the whole call with its status; the out entries are then not valid. */
 int fastlec_es_check_batch(const fastlec_es_circuit *const *cs, size_t k, const fastlec_es_options *opts,
                            fastlec_es_result *out);
 

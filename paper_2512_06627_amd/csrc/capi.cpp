@@ -220,6 +220,31 @@ int fastlec_es_check(const fastlec_es_circuit* c, const fastlec_es_options* opts
 
 int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const fastlec_es_options* opts,
                            fastlec_es_result* out) {
+    if (cs && out) {
+        // An entry's own error (a null handle) goes into that entry's verdict as a negative
+        // status; the other entries are checked as one batch, and the call returns the first
+        // entry's error once they are done.
+        std::vector<size_t> valid;
+        for (size_t i = 0; i < k; ++i)
+            if (cs[i]) valid.push_back(i);
+        if (valid.size() < k) {
+            std::vector<const fastlec_es_circuit*> sub;
+            for (size_t i : valid) sub.push_back(cs[i]);
+            std::vector<fastlec_es_result> r(valid.size());
+            if (!sub.empty()) {
+                const int st = fastlec_es_check_batch(sub.data(), sub.size(), opts, r.data());
+                if (st != FASTLEC_OK) return st;  // a failure of the whole call
+            }
+            for (size_t i = 0; i < k; ++i) {
+                std::memset(&out[i], 0, sizeof(out[i]));
+                out[i].verdict = FASTLEC_ERR_INVALID;
+            }
+            for (size_t t = 0; t < valid.size(); ++t) out[valid[t]] = r[t];
+            size_t first = 0;
+            while (cs[first]) ++first;
+            return fail(FASTLEC_ERR_INVALID, "null circuit at batch entry " + std::to_string(first));
+        }
+    }
     return guarded([&] {
         if (!cs || !out) throw Error{kErrInvalid, "null argument"};
         if (k == 0) return FASTLEC_OK;
@@ -229,7 +254,6 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
         std::vector<Circuit*> v;
         std::vector<HwRange> rs;
         for (size_t i = 0; i < k; ++i) {
-            if (!cs[i]) throw Error{kErrInvalid, "null circuit in batch"};
             v.push_back(const_cast<Circuit*>(&cs[i]->c));
             rs.push_back(range_of(v.back()->plan1.num_inputs, 0, 0));
         }

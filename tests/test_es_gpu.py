@@ -164,6 +164,27 @@ def test_batch_matches_single():
     assert [r["cex"] if r["verdict"] else None for r in res2] == [want[i] for i in perm]
 
 
+def test_batch_null_entry_reports_its_own_status():
+    """A null handle inside a batch: that entry's verdict is FASTLEC_ERR_INVALID, the other
+    entries carry the oracle's answers, and the call reports the first bad entry."""
+    import ctypes
+    gs = [miters.layered_cone_miter(2100 + i, 12, 600, fault_seed=(7 if i == 2 else None)) for i in range(4)]
+    circs = [es.fastlec_es_load_aig(g.to_aig()) for g in gs]
+    want = [oracle.check(g.to_aag(), threads=8) for g in gs]
+    handles = [circs[0].handle.value, None, circs[1].handle.value, circs[2].handle.value, None,
+               circs[3].handle.value]
+    arr = (ctypes.c_void_p * len(handles))(*handles)
+    res = (es.fastlec_es_result * len(handles))()
+    rc = es.lib().fastlec_es_check_batch(arr, len(handles), None, res)
+    assert rc == es.FASTLEC_ERR_INVALID
+    assert b"entry 1" in es.lib().fastlec_es_last_error()
+    assert res[1].verdict == es.FASTLEC_ERR_INVALID and res[4].verdict == es.FASTLEC_ERR_INVALID
+    assert res[1].patterns_evaluated == 0 and res[4].patterns_evaluated == 0
+    got = [res[j].cex if res[j].verdict else None for j in (0, 2, 3, 5)]
+    assert got == want
+    assert want[2] is not None
+
+
 def test_invalid_ranges_rejected():
     c = es.fastlec_es_load_aig(miters.minterm_miter(10, [3]).to_aag())
     with pytest.raises(es.EsError) as ei:

@@ -179,6 +179,20 @@ def test_runtime_model_properties():
         es.fastlec_es_predict(c, 5, 3)
 
 
+def test_batch_of_null_entries_reports_each_entry():
+    """Every entry null: no device is needed; each entry's verdict is FASTLEC_ERR_INVALID and the
+    call returns that status, naming the first entry."""
+    import ctypes
+    arr = (ctypes.c_void_p * 3)(None, None, None)
+    res = (es.fastlec_es_result * 3)()
+    for r in res:
+        r.verdict = 99
+    assert es.lib().fastlec_es_check_batch(arr, 3, None, res) == es.FASTLEC_ERR_INVALID
+    assert all(r.verdict == es.FASTLEC_ERR_INVALID for r in res)
+    assert b"entry 0" in es.lib().fastlec_es_last_error()
+    assert es.lib().fastlec_es_check_batch(None, 3, None, res) == es.FASTLEC_ERR_INVALID
+
+
 def test_specialized_kernels_compile_together():
     """Several circuits' kernels compiled in one call: each kernel reachable afterwards (a
     single compile of each circuit then costs nothing and reports its code object), and one
