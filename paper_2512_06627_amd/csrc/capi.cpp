@@ -3,11 +3,14 @@
 #include <atomic>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
-#include <map>
-#include <unordered_map>
+#include <exception>
 #include <fstream>
+#include <map>
 #include <sstream>
+#include <thread>
+#include <unordered_map>
 
 #include "runtime.hpp"
 
@@ -75,6 +78,17 @@ void fill_result(const Circuit& c, const HwRange& r, uint64_t best, fastlec_es_r
 // compile model's largest error here is 4%.  The LUT program (needed for the specialized
 // prediction) is only built when the interpreter's time could pay for a compile.
 constexpr double kCompileMargin = 1.2;
+
+// Specialized kernels in batches under AUTO (FASTLEC_ES_BATCH_JIT): 0 never, 1 by the runtime
+// model (default), 2 every cone whose kernel already exists (a test hook).
+int batch_jit_mode() {
+    static const int m = [] {
+        const char* e = std::getenv("FASTLEC_ES_BATCH_JIT");
+        const int x = e && *e ? std::atoi(e) : 1;
+        return x < 0 || x > 2 ? 1 : x;
+    }();
+    return m;
+}
 
 bool use_specialized(Circuit& c, const fastlec_es_options& o, const HwRange& r) {
     if (o.kernel == FASTLEC_KERNEL_SPECIALIZED) return true;
@@ -259,9 +273,10 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
         }
         // Cones the runtime model gives to the specialized kernel (AUTO only) run as their own
         // launches; the rest share interpreter launches.  Their kernels compile together as
-        // few hipRTC programs, so a cone is a candidate when its predicted saving beats its
-        // own share of the compile (kCompileMargin on the per-LUT part), and the candidates are
-        // taken when their summed saving also covers one program's fixed cost (same margin).
+        // hipRTC programs side by side in helper processes, so a cone is a candidate when its
+        // predicted saving beats its own part of the group's compile (kCompileMargin on its
+        // per-kernel time over the helpers), and the candidates are taken when their summed
+        // saving also covers the group's fixed cost (same margin).
         std::vector<size_t> spec;
         std::vector<uint8_t> is_spec(k, 0);
         if (o.kernel == FASTLEC_KERNEL_SPECIALIZED) {
@@ -269,27 +284,37 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
                 is_spec[i] = 1;
                 spec.push_back(i);
             }
-        } else if (o.kernel == FASTLEC_KERNEL_AUTO) {
+        } else if (o.kernel == FASTLEC_KERNEL_AUTO && batch_jit_mode() == 2) {
+            // Test hook: every cone whose kernel exists, whatever the model predicts.
+            for (size_t i = 0; i < k; ++i)
+                if (jit_ready(*v[i], specialized_waves_per_eu())) {
+                    is_spec[i] = 1;
+                    spec.push_back(i);
+                }
+            trace("batch: routing every cone whose kernel exists (%zu of %zu)", spec.size(), k);
+        } else if (o.kernel == FASTLEC_KERNEL_AUTO && batch_jit_mode() == 1) {
             // First an optimistic bound (a LUT count below any cover measured) over the cones that
             // could pay for a compile share: when even that saving cannot pay for one program, only
             // cones whose kernels already exist are considered, and no LUT program is built.
             std::vector<size_t> cand;
             std::vector<double> tis;
             double optimistic = 0;
+            const int helpers = compile_helpers();
+            const double fixed_ms = model_group_compile_fixed_ms(helpers);
             for (size_t i = 0; i < k; ++i) {
                 Circuit& c = *v[i];
                 const double patterns = 32.0 * (double)(rs[i].end - rs[i].begin);
                 const double ti = model_interp_ms(c.interp_gates(), c.interp_rows(), patterns);
-                if (ti < kCompileMargin * (model_compile_ms(0) / 64.0)) continue;  // cheap cone: no LUT program
+                if (ti < kCompileMargin * model_group_compile_kernel_ms(0, helpers)) continue;  // cheap cone
                 cand.push_back(i);
                 tis.push_back(ti);
                 const uint32_t lo = model_lut_steps_low(c.plan1.num_ands_tfi);
                 const double ts = model_specialized_ms(lo, patterns);
                 const double own = jit_ready(c, specialized_waves_per_eu()) ? 0.0
-                                   : kCompileMargin * (model_compile_ms(lo) - model_compile_ms(0));
+                                   : kCompileMargin * model_group_compile_kernel_ms(lo, helpers);
                 if (ts + own < ti) optimistic += ti - ts - own;
             }
-            const bool program_possible = optimistic >= kCompileMargin * model_compile_ms(0);
+            const bool program_possible = optimistic >= kCompileMargin * fixed_ms;
             // The LUT programs the decision needs, mapped on host threads in parallel.
             std::vector<Circuit*> mapped;
             for (size_t i : cand)
@@ -305,14 +330,17 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
                 const uint32_t luts = c.lut_program().lut_steps;
                 const double ts = model_specialized_ms(luts, patterns);
                 const double own = jit_ready(c, specialized_waves_per_eu()) ? 0.0
-                                   : kCompileMargin * (model_compile_ms(luts) - model_compile_ms(0));
+                                   : kCompileMargin * model_group_compile_kernel_ms(luts, helpers);
                 if (ts + own < ti) {
                     is_spec[i] = 1;
                     spec.push_back(i);
                     saving += ti - ts - own;
                 }
             }
-            if (saving < kCompileMargin * model_compile_ms(0)) {
+            trace("batch: %zu candidate cones, %zu routed, predicted saving %.1f ms against a group compile "
+                  "fixed cost of %.1f ms (%d helpers)",
+                  cand.size(), spec.size(), saving, fixed_ms, helpers);
+            if (saving < kCompileMargin * fixed_ms) {
                 std::vector<size_t> kept;
                 for (size_t i : spec) {  // not worth a program: only cones already compiled stay
                     if (jit_ready(*v[i], specialized_waves_per_eu())) kept.push_back(i);
@@ -321,38 +349,47 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
                 spec.swap(kept);
             }
         }
-        // Compile the routed cones' kernels together.  Under AUTO a cone whose kernel does not
-        // compile runs on the interpreter instead (the whole program is retried per cone first).
-        std::vector<std::shared_ptr<JitKernel>> jk;
-        std::vector<double> cms;
-        if (!spec.empty()) {
-            std::vector<Circuit*> sc;
-            for (size_t i : spec) sc.push_back(v[i]);
-            try {
-                jk = jit_kernels(sc, specialized_waves_per_eu(), &cms);
-            } catch (const Error& e) {
-                if (o.kernel == FASTLEC_KERNEL_SPECIALIZED) throw;
-                trace("batch: grouped compile failed (%s); compiling per cone", e.msg.c_str());
-                jk.assign(sc.size(), nullptr);
-                cms.assign(sc.size(), 0.0);
-                std::vector<size_t> kept;
-                std::vector<std::shared_ptr<JitKernel>> kept_k;
-                std::vector<double> kept_ms;
-                for (size_t j = 0; j < sc.size(); ++j) {
-                    try {
-                        double ms = 0;
-                        kept_k.push_back(jit_kernel(*sc[j], specialized_waves_per_eu(), &ms));
-                        kept_ms.push_back(ms);
-                        kept.push_back(spec[j]);
-                    } catch (const Error&) {
-                        is_spec[spec[j]] = 0;  // back to the interpreter
-                    }
-                }
-                spec.swap(kept);
-                jk.swap(kept_k);
-                cms.swap(kept_ms);
+        // Compile the routed cones' kernels together, on a host thread while the interpreter
+        // cones run on the device (compiles need no GPU).  Under AUTO a cone whose kernel does
+        // not compile (the group is retried cone by cone first) runs on the interpreter
+        // afterwards, as a launch of its own.  The thread only fills jk and cms; the guard
+        // joins it on every path out of this call.
+        std::vector<Circuit*> sc;
+        for (size_t i : spec) sc.push_back(v[i]);
+        std::vector<std::shared_ptr<JitKernel>> jk(spec.size());
+        std::vector<double> cms(spec.size(), 0.0);
+        std::exception_ptr compile_error;
+        struct Joiner {
+            std::thread t;
+            ~Joiner() {
+                if (t.joinable()) t.join();
             }
-        }
+        } compile_job;
+        const int spec_waves = specialized_waves_per_eu();
+        const bool spec_forced = o.kernel == FASTLEC_KERNEL_SPECIALIZED;
+        if (!sc.empty())
+            compile_job.t = std::thread([&sc, &jk, &cms, &compile_error, spec_waves, spec_forced] {
+                try {
+                    try {
+                        jk = jit_kernels(sc, spec_waves, &cms);
+                    } catch (const Error& e) {
+                        if (spec_forced) throw;
+                        trace("batch: grouped compile failed (%s); compiling per cone", e.msg.c_str());
+                        for (size_t j = 0; j < sc.size(); ++j) {
+                            double ms = 0;
+                            try {
+                                jk[j] = jit_kernel(*sc[j], spec_waves, &ms);
+                                cms[j] = ms;
+                            } catch (const Error&) {
+                                jk[j] = nullptr;  // back to the interpreter
+                                cms[j] = 0;
+                            }
+                        }
+                    }
+                } catch (...) {
+                    compile_error = std::current_exception();
+                }
+            });
         // Interpreter cones predicted to take at least a millisecond gain nothing from sharing
         // a launch (a launch costs tens of microseconds) and lose their own schedule to the
         // group's, which is sized for the group's largest cone: they run as their own launches.
@@ -416,7 +453,7 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
         }
         for (size_t i = 0; i < k; ++i)
             if (!is_spec[i] && !is_alone[i]) out[i].kernel_ms = total_ms;
-        for (size_t i : alone) {
+        auto run_alone = [&](size_t i) {
             std::vector<Circuit*> one{v[i]};
             std::vector<HwRange> r1{rs[i]};
             Schedule sch = default_schedule(dev, one, &o, rs[i].end - rs[i].begin);
@@ -429,10 +466,17 @@ int fastlec_es_check_batch(const fastlec_es_circuit* const* cs, size_t k, const 
             out[i].kernel_ms = ms;
             out[i].predicted_ms = model_interp_ms(v[i]->interp_gates(), v[i]->interp_rows(),
                                                   32.0 * (double)(rs[i].end - rs[i].begin));
-        }
+        };
+        for (size_t i : alone) run_alone(i);
+        if (compile_job.t.joinable()) compile_job.t.join();
+        if (compile_error) std::rethrow_exception(compile_error);
         if (!spec.empty()) {
             for (size_t j = 0; j < spec.size(); ++j) {
                 const size_t i = spec[j];
+                if (!jk[j]) {
+                    run_alone(i);
+                    continue;
+                }
                 uint64_t best = ~0ull;
                 double ms = 0;
                 run_jit(dev, *v[i], *jk[j], rs[i], o.tile_words ? 2ull * o.tile_words : 0, stream, nullptr, &best, &ms);

@@ -18,6 +18,12 @@ constexpr double kSpecT0Ms = 0.0135;
 constexpr double kSpecLutPassesPerS = 6.08e11;
 constexpr double kCompileC0Ms = 101.7;
 constexpr double kCompileMsPerLut = 0.00664;
+// Multi-kernel programs (GPU machine host, comgr's cache off): 16 kernels of about 500 LUT steps
+// 0.39 s as one program, 8 of about 4,000 0.45 s, 2 small ones 0.14-0.16 s in helpers against
+// the fixed 0.10 s in the process: each kernel adds about 12 ms besides its LUT steps, and a
+// helper's start-up about 45 ms.
+constexpr double kCompileMsPerKernel = 12.0;
+constexpr double kHelperStartMs = 45.0;
 constexpr double kLutsPerGate = 0.30;
 constexpr double kLutsPerGateLow = 0.20;  // below every cover measured (0.23 layered cones, 0.28 multipliers)
 }  // namespace model
@@ -38,6 +44,14 @@ double model_specialized_ms(uint32_t lut_steps, double patterns) {
 }
 
 double model_compile_ms(uint32_t lut_steps) { return model::kCompileC0Ms + model::kCompileMsPerLut * lut_steps; }
+
+double model_group_compile_fixed_ms(int helpers) {
+    return model::kCompileC0Ms + (helpers > 0 ? model::kHelperStartMs : 0.0);
+}
+
+double model_group_compile_kernel_ms(uint32_t lut_steps, int helpers) {
+    return (model::kCompileMsPerKernel + model::kCompileMsPerLut * lut_steps) / (double)std::max(1, helpers);
+}
 
 uint32_t model_lut_steps_estimate(uint32_t and_gates) {
     return (uint32_t)((double)and_gates * model::kLutsPerGate + 0.5);

@@ -22,6 +22,12 @@ double model_interp_ms(uint32_t gates, uint32_t rows, double patterns);
 int model_interp_tier(uint32_t rows);
 double model_specialized_ms(uint32_t lut_steps, double patterns);
 double model_compile_ms(uint32_t lut_steps);
+// Compiles of several kernels at once (a batch's routed cones): with `helpers` compile helper
+// processes (0: in this process) the programs compile side by side, so the group's wall time is
+// about one program's fixed cost (plus a helper's start-up) and each kernel adds its own part
+// (a per-kernel cost inside a multi-kernel program plus c1 per LUT step) over the helpers.
+double model_group_compile_fixed_ms(int helpers);
+double model_group_compile_kernel_ms(uint32_t lut_steps, int helpers);
 
 // LUT steps expected for a cone of `and_gates` AND gates before its LUT program is built
 // (measured covers: 0.28 LUTs per gate for the 16x16 multiplier miter, 0.23 for layered cones;

@@ -34,7 +34,7 @@ struct FakeEvent {
     std::chrono::steady_clock::time_point t;
 };
 
-int g_device = 0;
+thread_local int g_device = 0;  // the current device is per host thread, as in HIP
 
 uint32_t pi_word(uint32_t i, uint64_t hw) {
     static const uint32_t kc[5] = {0xAAAAAAAAu, 0xCCCCCCCCu, 0xF0F0F0F0u, 0xFF00FF00u, 0xFFFF0000u};
@@ -253,12 +253,14 @@ uint64_t noalloc_check(Device&, Circuit&, const fastlec_es_options&, const HwRan
 double valu_probe(Device&, uint32_t, uint32_t, uint32_t, hipStream_t, double*) {
     throw Error{kErrDevice, "host stand-in: no probe"};
 }
-Schedule autotune(Device&, const std::vector<Circuit*>&, const std::vector<HwRange>&, hipStream_t, bool) {
-    throw Error{kErrDevice, "host stand-in: no batch autotune"};
+// Batches: the default schedule instead of timed candidates, and the grouped launch as one
+// interpreter run over the group's cones (evaluated on the host like any launch here).
+Schedule autotune(Device& dev, const std::vector<Circuit*>& cs, const std::vector<HwRange>&, hipStream_t, bool) {
+    return default_schedule(dev, cs, nullptr);
 }
-void run_batch_graph(Device&, const std::vector<Circuit*>&, const std::vector<HwRange>&, const Schedule&, hipStream_t,
-                     std::vector<uint64_t>&, double*) {
-    throw Error{kErrDevice, "host stand-in: no batch graphs"};
+void run_batch_graph(Device& dev, const std::vector<Circuit*>& cs, const std::vector<HwRange>& rs, const Schedule& sch,
+                     hipStream_t stream, std::vector<uint64_t>& best, double* ms) {
+    run_interp(dev, cs, rs, sch, stream, nullptr, best, ms);
 }
 
 int specialized_waves_per_eu() { return 3; }

@@ -6,7 +6,10 @@
 // submitter threads, poller threads that take tickets from the submitters, a stats reader, and a
 // second server destroyed while jobs and compiles are still in flight.  Every answer must equal
 // the same circuit checked alone with fastlec_es_check.  In between, four threads run plain
-// checks (each kernel choice) and predictions on the same handles at once.
+// checks (each kernel choice) and predictions on the same handles at once, then two threads run
+// batches of those handles and fresh ones (each kernel choice; with FASTLEC_ES_BATCH_JIT=2 AUTO
+// routes the handles whose kernels exist to them, so each batch's compile thread runs beside its
+// interpreter launches over the fresh handles).
 //
 // Built with -fsanitize=thread together with the library's host sources and fake_device.cpp
 // (a host stand-in for the GPU: the HIP runtime finds no device in a process built with the
@@ -181,6 +184,44 @@ int main(int argc, char** argv) {
     for (auto& t : pt) t.join();
     std::printf("plain checks from 4 threads: %d wrong\n", plain_bad.load());
     if (plain_bad.load()) return fail("concurrent plain checks", 0);
+
+    std::atomic<int> batch_bad{0};
+    std::vector<std::thread> bt;
+    for (int t = 0; t < 2; ++t)
+        bt.emplace_back([&, t] {
+            // The checked handles (kernels compiled above) and a fresh copy of each circuit.
+            std::vector<fastlec_es_circuit*> mix;
+            std::vector<uint64_t> mix_want;
+            for (size_t i = 0; i < cs.size(); ++i) {
+                const std::string s = read_file(argv[1 + i]);
+                fastlec_es_circuit* c = nullptr;
+                if (fastlec_es_load_aig(s.data(), s.size(), &c)) {
+                    batch_bad.fetch_add(1);
+                    return;
+                }
+                mix.push_back((i + (size_t)t) % 2 ? c : cs[i]);
+                mix.push_back((i + (size_t)t) % 2 ? cs[i] : c);
+                mix_want.push_back(want[i]);
+                mix_want.push_back(want[i]);
+            }
+            for (int kern : {FASTLEC_KERNEL_AUTO, FASTLEC_KERNEL_INTERP, FASTLEC_KERNEL_SPECIALIZED}) {
+                fastlec_es_options bo;
+                fastlec_es_options_init(&bo);
+                bo.kernel = kern;
+                std::vector<fastlec_es_result> r(mix.size());
+                if (fastlec_es_check_batch(mix.data(), mix.size(), &bo, r.data())) {
+                    batch_bad.fetch_add(1);
+                    continue;
+                }
+                for (size_t i = 0; i < mix.size(); ++i)
+                    if (answer(r[i]) != mix_want[i]) batch_bad.fetch_add(1);
+            }
+            for (size_t i = 0; i < mix.size(); ++i)
+                if (mix[i] != cs[i / 2]) fastlec_es_free(mix[i]);
+        });
+    for (auto& t : bt) t.join();
+    std::printf("batches from 2 threads: %d wrong\n", batch_bad.load());
+    if (batch_bad.load()) return fail("concurrent batches", 0);
 
     // Teardown with work in flight: jobs queued and running, compiles possibly under way.
     rc = fastlec_es_server_create(&o, size_t(64) << 30, &srv);

@@ -11,6 +11,7 @@ thread.  Any sanitizer report fails the test.
 """
 import concurrent.futures
 import os
+import re
 import subprocess
 
 import pytest
@@ -65,11 +66,16 @@ def circuits(tmp_path_factory):
 @pytest.mark.parametrize("jit", ["1", "2"])
 def test_server_threads_have_no_data_races(driver, circuits, jit):
     env = dict(os.environ, FASTLEC_ES_SERVER_JIT=jit, FASTLEC_ES_SERVER_RATE="1000000000",
-               FASTLEC_ES_SERVER_STEP_MS="1", TSAN_OPTIONS="halt_on_error=1 exitcode=66")
+               FASTLEC_ES_SERVER_STEP_MS="1", FASTLEC_ES_TRACE="1", FASTLEC_ES_BATCH_JIT="2",
+               TSAN_OPTIONS="halt_on_error=1 exitcode=66")
     r = subprocess.run([driver] + circuits, capture_output=True, text=True, timeout=600, env=env)
     assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-8000:])
     assert "ThreadSanitizer" not in r.stderr, r.stderr[-8000:]
     assert r.stdout.strip().endswith("ok 96"), r.stdout
+    assert "batches from 2 threads: 0 wrong" in r.stdout, r.stdout
+    # AUTO batches routed cones to their (existing) kernels: each such batch ran its compile
+    # thread beside its interpreter launches
+    assert "batch: routing every cone whose kernel exists" in r.stderr, r.stderr[-3000:]
     line = [ln for ln in r.stdout.splitlines() if ln.startswith("server:")][0]
     assert " 0 mismatches, 0 errors" in line, line
     if jit == "2":
