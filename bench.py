@@ -121,8 +121,9 @@ def batch_leg(es, stream, seed: int = 4, count: int = 256, faulty: int = 26, n_r
     with an injected fault), checked four ways with identical answers: one plain check per cone on
     the interpreter; one batched call on the interpreter (persistent grouped launches, autotuned,
     hipGraph); one batched call with the runtime model's routing (large cones on their compiled
-    specialized kernels, compiled together on the first call); one plain check per cone with the
-    model's kernel choice once those kernels exist."""
+    specialized kernels, compiled in helper processes on the first call while the other cones run
+    on the interpreter); one plain check per cone with the model's kernel choice once those
+    kernels exist."""
     import miters
     t0 = time.perf_counter()
     cones, work = [], 0
