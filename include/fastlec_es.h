@@ -216,8 +216,10 @@ typedef struct {
  * or the lowest failing pattern known).  Job descriptors and best-so-far values stay in a
  * device-resident job table between steps.  A job whose remaining interpreter time is
  * estimated well above the time to compile its specialized kernel is compiled on a
- * background thread meanwhile; its later slices run on that kernel (same ascending slices,
- * same answer).  FASTLEC_ES_SERVER_JIT=0 turns this off.  Slices are sized for steps of
+ * background thread meanwhile (one thread per compile helper process, each compiling one job's
+ * kernel in a helper; without the helper program one thread compiling up to eight jobs' kernels
+ * as one program); its later slices run on that kernel (same ascending slices, same answer).
+ * FASTLEC_ES_SERVER_JIT=0 turns this off.  Slices are sized for steps of
  * FASTLEC_ES_SERVER_STEP_MS (default 10) ms from a running rate estimate that starts at
  * FASTLEC_ES_SERVER_RATE node*patterns/s (default 1e14).  opts: device, stream, schedule
  * fields; the word range, deadline and cancel fields are ignored.  budget_bytes > 0. */
