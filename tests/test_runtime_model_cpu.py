@@ -5,7 +5,9 @@ publishes through fastlec_es_predict.
 The server compiles a job's specialized kernel when its remaining interpreter time at its share
 of the device (the jobs on the interpreter share each step equally) exceeds the predicted
 specialized time of that work plus twice the predicted compile time.  The model driver (tests/sanitize/model_driver.cpp, built with
-AddressSanitizer and UBSan) calls the library's decision function directly.
+AddressSanitizer and UBSan) calls the library's decision function directly.  The batch's price
+of a grouped compile in helper processes is checked against compile times measured on MI355X's
+host.
 """
 import os
 import re
@@ -81,3 +83,36 @@ def test_server_tier_rule_follows_the_model(driver):
     assert wanted[("layered34", 1 << 28, 1)] == 1
     assert all(wanted[("mult6", 64, s)] == 0 for s in (1, 8, 64))
     assert wanted[("mult16", 1 << 26, 1)] == 0 and wanted[("mult16", 1 << 26, 8)] == 1
+
+
+# Grouped compiles measured on the GPU machine's host (16 cores, comgr's compile cache off): k kernels
+# of layered cones (n = 24, about N AND gates; generator seeds 700 onward, in this order) split
+# into p programs compiled side by side by compile helper processes; wall seconds.
+GROUP_COMPILES = [((600, 2), {1: 0.155, 2: 0.141}), ((600, 4), {1: 0.183, 2: 0.156, 4: 0.152}),
+                  ((600, 16), {1: 0.344, 2: 0.241, 4: 0.185, 8: 0.174}), ((2000, 2), {1: 0.158, 2: 0.146}),
+                  ((2000, 4), {1: 0.192, 2: 0.163, 4: 0.139}),
+                  ((2000, 16), {1: 0.390, 2: 0.260, 4: 0.200, 8: 0.163}),
+                  ((15000, 8), {1: 0.450, 2: 0.303, 4: 0.210, 8: 0.171})]
+
+
+def test_group_compile_model_against_measured_compiles(driver):
+    """The batch's price of a grouped compile (fixed cost with a helper's start-up, then each
+    kernel's part over the helpers) against the measured wall times: never more than 5% low (a low
+    price would route cones whose compile does not pay) and at most 20% high."""
+    rows, want = [], []
+    seed = 700
+    for (gates, k), by_programs in GROUP_COMPILES:
+        luts = []
+        for _ in range(k):
+            c = es.fastlec_es_load_aig(miters.layered_cone_miter(seed, 24, gates).to_aig())
+            seed += 1
+            luts.append(_lut_steps(c))
+        for p, seconds in by_programs.items():
+            rows.append(f"{p} {k} " + " ".join(map(str, luts)))
+            want.append(((gates, k, p), 1000.0 * seconds))
+    r = subprocess.run([driver, "group"], input="\n".join(rows) + "\n", capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-3000:]
+    got = [float(x) for x in r.stdout.split()]
+    assert len(got) == len(want)
+    for pred, (case, ms) in zip(got, want):
+        assert 0.95 * ms <= pred <= 1.20 * ms, (case, pred, ms)
